@@ -1,0 +1,387 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test ties an oracle function to something other than itself: an integer
+identity checked exhaustively, a library routine that computes the same
+quantity another way (scipy's DCT, numpy's Chebyshev module, numpy/LAPACK
+least squares), a closed form, a special case with a textbook answer, or
+brute force on tiny inputs.  None of these tests touches the GPU.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import numpy.polynomial.chebyshev as npc
+import pytest
+import scipy.fft
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Aliasing fold: Lobatto analogue of Lemma 3.1 (Sec. 3.1)
+# --------------------------------------------------------------------------
+
+def test_fold_integer_identity_exhaustive():
+    """cos(n k pi/N) = cos(m k pi/N) for every node k, as integers mod 2N.
+
+    For each N <= 39 and n < 6N, the folded m lies in 0..N, satisfies
+    n k = +-m k (mod 2N) for every k, and is the only index in 0..N that
+    does (so the alias is unique and the block of A has one 1 per column).
+    """
+    bad = 0
+    for N in range(1, 40):
+        ks = range(N + 1)
+        for n in range(6 * N):
+            m = O.fold(n, N)
+            assert 0 <= m <= N
+            ok = all((n * k - m * k) % (2 * N) == 0 or (n * k + m * k) % (2 * N) == 0
+                     for k in ks)
+            if not ok:
+                bad += 1
+            others = [mm for mm in range(N + 1) if mm != m and all(
+                (n * k - mm * k) % (2 * N) == 0 or (n * k + mm * k) % (2 * N) == 0
+                for k in ks)]
+            assert not others, (n, N, m, others)
+    assert bad == 0
+
+
+def test_fold_single_node():
+    # one node at x = 1: every T_n(1) = 1 = T_0(1)
+    assert all(O.fold(n, 0) == 0 for n in range(50))
+
+
+def test_fold_numeric_against_numpy_chebval():
+    """T_n at the Lobatto nodes equals T_fold(n) there (numpy's Chebyshev
+    evaluation, independent of the oracle's recurrence)."""
+    for N in [1, 2, 3, 5, 8, 13]:
+        x = O.lobatto_nodes(N)
+        for n in range(5 * N + 3):
+            en = np.zeros(n + 1); en[n] = 1
+            m = O.fold(n, N)
+            em = np.zeros(m + 1); em[m] = 1
+            assert np.allclose(npc.chebval(x, en), npc.chebval(x, em), atol=1e-12)
+
+
+def test_chebyshev_evaluations_agree():
+    x = np.linspace(-1, 1, 37)
+    tab = O.cheb_T_recurrence(20, x)
+    for n in range(21):
+        e = np.zeros(n + 1); e[n] = 1
+        ref = npc.chebval(x, e)
+        assert np.allclose(tab[n], ref, atol=1e-12)
+        assert np.allclose(O.cheb_T(n, x), ref, atol=1e-12)
+
+
+def test_fold_by_hand_D1():
+    """D = 1, degrees 0..7 on N = 3 and N = 4 (P6): fold tables by hand.
+    N=3: period 6, n -> 0 1 2 3 2 1 0 1;  N=4: period 8, n -> 0 1 2 3 4 3 2 1."""
+    assert [O.fold(n, 3) for n in range(8)] == [0, 1, 2, 3, 2, 1, 0, 1]
+    assert [O.fold(n, 4) for n in range(8)] == [0, 1, 2, 3, 4, 3, 2, 1]
+    S = np.arange(8, dtype=np.int32)[:, None]
+    plan = O.build_plan(S, np.array([[3], [4]], dtype=np.int32))
+    assert plan.alias.tolist() == [[0, 1, 2, 3, 2, 1, 0, 1], [0, 1, 2, 3, 4, 3, 2, 1]]
+    # grid 0 bins 0..3 hold {0,6}, {1,5,7}, {2,4}, {3}; grid 1 bins 0..4
+    assert plan.perm[0].tolist() == [0, 6, 1, 5, 7, 2, 4, 3]
+    assert plan.perm[1].tolist() == [0, 1, 7, 2, 6, 3, 5, 4]
+    assert plan.seg_off.tolist() == [0, 2, 5, 7, 8, 9, 11, 13, 15, 16]
+    assert plan.M == 9
+    # degrees 1 and 7 alias together on both N=3 and N=4, so that stack
+    # cannot separate them; N=3 with N=5 separates every degree 0..7
+    assert not O.fold_injective(S, [[3], [4]])
+    assert O.fold_injective(S, [[3], [5]])
+    assert not O.fold_injective(S, [[3], [3]])
+
+
+# --------------------------------------------------------------------------
+# DCT-I (interpolation normalisation)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", list(range(1, 31)) + [47, 63])
+def test_dct1_matches_scipy(N):
+    rng = np.random.default_rng(N)
+    v = rng.standard_normal(N + 1)
+    g = np.ones(N + 1); g[0] = g[N] = 0.5
+    ref = g * scipy.fft.dct(v, type=1) / N
+    assert np.allclose(O.dct1_matrix(N) @ v, ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 7, 9, 16, 24])
+def test_dct1_closed_form_chebyshev_samples(N):
+    """Samples of T_n (numpy chebval) transform to e_fold(n) exactly."""
+    x = O.lobatto_nodes(N)
+    C = O.dct1_matrix(N)
+    for n in range(4 * N + 2):
+        e = np.zeros(n + 1); e[n] = 1
+        a = C @ npc.chebval(x, e)
+        want = np.zeros(N + 1); want[O.fold(n, N)] = 1
+        assert np.allclose(a, want, atol=1e-13), (N, n)
+
+
+@pytest.mark.parametrize("N", [0, 1, 3, 8, 24])
+def test_dct1_round_trip(N):
+    rng = np.random.default_rng(7 + N)
+    v = rng.standard_normal(N + 1)
+    C, E = O.dct1_matrix(N), O.dct1_eval_matrix(N)
+    assert np.allclose(E @ (C @ v), v, atol=1e-13)
+    assert np.allclose(C @ (E @ v), v, atol=1e-13)
+
+
+@pytest.mark.parametrize("grid", [(3, 5), (6, 2), (4, 1, 3), (0, 4), (2, 0, 5)])
+def test_dct_grid_full_resolution(grid):
+    """P5: a coefficient tensor of matching size evaluated on its tensor grid
+    (numpy chebgrid) is recovered exactly by the separable transform.
+    Unequal extents catch a transposed or misordered axis."""
+    rng = np.random.default_rng(sum(grid))
+    shape = tuple(g + 1 for g in grid)
+    Ct = rng.standard_normal(shape)
+    xs = [O.lobatto_nodes(g) for g in grid]
+    if len(grid) == 2:
+        vals = npc.chebgrid2d(xs[0], xs[1], Ct)
+    else:
+        vals = npc.chebgrid3d(xs[0], xs[1], xs[2], Ct)
+    got = O.dct_grid(vals.reshape(-1), grid).reshape(shape)
+    assert np.allclose(got, Ct, atol=1e-12)
+    back = O.idct_grid(Ct.reshape(-1), grid).reshape(shape)
+    assert np.allclose(back, vals, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Supports (Sec. 2 cardinalities)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("D,d,count", [(2, 16, 153), (6, 12, 18564), (12, 10, 646646),
+                                       (20, 4, 10626), (3, 5, 56)])
+def test_total_degree_counts(D, d, count):
+    S = W.total_degree_support(D, d)
+    assert len(S) == count == math.comb(d + D, d)
+
+
+def test_total_degree_support_is_the_set_in_order():
+    for D, d in [(1, 5), (2, 4), (3, 3), (4, 2)]:
+        S = W.total_degree_support(D, d)
+        brute = [t for t in itertools.product(range(d + 1), repeat=D) if sum(t) <= d]
+        assert [tuple(r) for r in S.tolist()] == brute   # product() is lexicographic
+
+
+def test_euclidean_support():
+    for D, d in [(2, 5.0), (3, 4.5)]:
+        S = W.euclidean_degree_support(D, d)
+        brute = [t for t in itertools.product(range(int(d) + 1), repeat=D)
+                 if sum(v * v for v in t) <= d * d]
+        assert [tuple(r) for r in S.tolist()] == brute
+
+
+# --------------------------------------------------------------------------
+# The operator A and the plan
+# --------------------------------------------------------------------------
+
+def _chebval_nd(support, coeffs, grid):
+    """Samples of sum_n c_n T_n on a tensor grid via numpy's chebval."""
+    xs = [O.lobatto_nodes(int(g)) for g in grid]
+    mesh = np.meshgrid(*xs, indexing="ij")
+    out = np.zeros(mesh[0].shape)
+    for j, n in enumerate(np.asarray(support)):
+        term = np.full(mesh[0].shape, float(coeffs[j]))
+        for i, ni in enumerate(n):
+            e = np.zeros(int(ni) + 1); e[int(ni)] = 1
+            term = term * npc.chebval(mesh[i], e)
+        out += term
+    return out.reshape(-1)
+
+
+def test_A_columns_from_definition():
+    """Each column of A^(l) is the DCT of T_n's samples (Sec. 3.1, b = A c = F p):
+    transform the samples of one basis polynomial and read where the 1 lands."""
+    S = W.total_degree_support(3, 6)
+    grids = np.array([[2, 3, 1], [4, 0, 2], [3, 5, 4]], dtype=np.int32)
+    plan = O.build_plan(S, grids)
+    for l, g in enumerate(grids):
+        for j in range(len(S)):
+            e = np.zeros(len(S)); e[j] = 1
+            t = O.dct_grid(_chebval_nd(S, e, g), g)
+            nz = np.flatnonzero(np.abs(t) > 1e-9)
+            assert nz.tolist() == [plan.alias[l, j]]
+            assert abs(t[nz[0]] - 1) < 1e-12
+
+
+def test_operator_identity_planted():
+    """P3: A c = F f for f = sum c_n T_n sampled by brute force."""
+    for prob in [W.config1(), W.small_problem(3, 3, 7, 1, 6, 5),
+                 W.small_problem(4, 4, 5, 0, 4, 6)]:
+        plan = O.build_plan(prob.support, prob.grids)
+        samples = O.sample_problem(prob)
+        trans = [O.dct_grid(samples[l], prob.grids[l]) for l in range(prob.K)]
+        b = O.rhs_from_transforms(plan, trans)
+        A = O.dense_A(plan)
+        assert np.allclose(A @ prob.coeffs, b, atol=1e-12)
+        # empty bins carry nothing
+        for l in range(prob.K):
+            empty = np.setdiff1d(np.arange(plan.points[l]), plan.alias[l])
+            assert np.allclose(trans[l][empty], 0, atol=1e-12)
+
+
+def test_planted_sampler_matches_numpy():
+    prob = W.small_problem(5, 3, 5, 1, 5, 2)
+    for g in prob.grids:
+        assert np.allclose(O.sample_planted(prob.support, prob.coeffs, g),
+                           _chebval_nd(prob.support, prob.coeffs, g), atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_plan_invariants(seed):
+    """P10: one 1 per column per grid; rows sorted by (bin, position);
+    segment lengths sum to n per grid; M_l <= min(P_l, n)."""
+    prob = W.small_problem(seed, 4, 6, 0, 5, 5)
+    plan = O.build_plan(prob.support, prob.grids)
+    A = O.dense_A(plan)
+    assert np.all(A.sum(axis=0) == plan.K)
+    n = plan.n
+    flat = plan.perm.reshape(-1)
+    for l in range(plan.K):
+        r0, r1 = plan.rows_of_grid(l)
+        assert r1 - r0 <= min(plan.points[l], n)
+        keys = [(plan.alias[l, j], j) for j in plan.perm[l]]
+        assert all(keys[i] < keys[i + 1] for i in range(n - 1))
+        assert plan.seg_off[r0] == l * n
+        assert np.all(np.diff(plan.bin_id[r0:r1]) > 0)
+        for r in range(r0, r1):
+            js = flat[plan.seg_off[r]:plan.seg_off[r + 1]]
+            assert len(js) > 0
+            assert np.all(plan.alias[l, js] == plan.bin_id[r])
+            assert np.all(plan.rowmap[l, js] == r)
+    assert plan.seg_off[-1] == plan.K * n
+    assert np.all(A[plan.rowmap[0], np.arange(n)] == 1)
+
+
+# --------------------------------------------------------------------------
+# Least squares and recovery (Sec. 3.4, Alg. 3)
+# --------------------------------------------------------------------------
+
+def test_exact_recovery_config1():
+    """P4: a planted polynomial on the support is recovered exactly."""
+    prob = W.config1()
+    c, plan, _ = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "qr")
+    assert O.max_rel_err(c, prob.coeffs) < 1e-13
+    full, kappa = O.rank_check(plan)
+    assert full and kappa < 1e4
+
+
+@pytest.mark.parametrize("args", [(11, 3, 8, 2, 7, 6), (12, 5, 5, 0, 5, 12)])
+def test_exact_recovery_small(args):
+    prob = W.small_problem(*args)
+    plan = O.build_plan(prob.support, prob.grids)
+    assert O.rank_check(plan)[0]
+    for method in ("qr", "normal"):
+        c, _, _ = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), method)
+        assert O.max_rel_err(c, prob.coeffs) < 1e-12
+
+
+def test_sample_space_least_squares_agrees():
+    """P7: least squares on B_ij = T_n_j(x_i) (no DCT, no aliasing) gives the
+    same coefficients for a polynomial on the support."""
+    prob = W.config1()
+    Bs, fs = [], []
+    for g in prob.grids:
+        xs = [O.lobatto_nodes(int(v)) for v in g]
+        X = np.stack([m.reshape(-1) for m in np.meshgrid(*xs, indexing="ij")], axis=1)
+        V0 = npc.chebvander(X[:, 0], 16)
+        V1 = npc.chebvander(X[:, 1], 16)
+        Bs.append(V0[:, prob.support[:, 0]] * V1[:, prob.support[:, 1]])
+        fs.append(_chebval_nd(prob.support, prob.coeffs, g))
+    B, f = np.vstack(Bs), np.concatenate(fs)
+    cB = np.linalg.lstsq(B, f, rcond=None)[0]
+    c, _, _ = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "qr")
+    assert np.allclose(cB, prob.coeffs, atol=1e-12)
+    assert np.allclose(c, cB, atol=1e-12)
+
+
+def test_least_squares_methods_agree_inconsistent():
+    """For f outside the span (exp-cos), QR, normal equations and LAPACK's
+    SVD-based lstsq on the explicit A give one minimiser, and the normal
+    residual A^T(b - A c) vanishes there."""
+    prob = W.small_problem(21, 3, 7, 2, 6, 6, W.FAMILY_EXPCOS)
+    samples = O.sample_problem(prob)
+    c_qr, plan, b = O.fct_solve(prob.support, prob.grids, samples, "qr")
+    c_ne, _, _ = O.fct_solve(prob.support, prob.grids, samples, "normal")
+    c_sv = np.linalg.lstsq(O.dense_A(plan), b, rcond=None)[0]
+    assert O.max_rel_err(c_qr, c_sv) < 1e-12
+    assert O.max_rel_err(c_ne, c_sv) < 1e-12
+    assert np.abs(O.normal_residual(plan, b, c_qr)).max() < 1e-13 * np.abs(b).max()
+    # the system is inconsistent: the residual itself is not zero
+    assert np.linalg.norm(b - O.dense_A(plan) @ c_qr) > 1e-8
+
+
+def test_certificate_bound():
+    """P8: ||c - c*||_2 <= ||A^T(b - A c)||_2 / sigma_min(A)^2 for any c, and
+    A^T A is the integer collision-count matrix with diagonal K."""
+    prob = W.small_problem(22, 3, 6, 2, 6, 6, W.FAMILY_EXPCOS)
+    assert O.rank_check(O.build_plan(prob.support, prob.grids))[0]
+    c_star, plan, b = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "qr")
+    G = O.gram_matrix(plan)
+    assert np.all(G == np.round(G)) and np.all(np.diag(G) == plan.K)
+    smin2 = np.linalg.eigvalsh(G)[0]
+    rng = np.random.default_rng(3)
+    for scale in [1e-2, 1e-6]:
+        c = c_star + scale * rng.standard_normal(plan.n)
+        bound = np.linalg.norm(O.normal_residual(plan, b, c)) / smin2
+        assert np.linalg.norm(c - c_star) <= bound * (1 + 1e-9)
+
+
+def test_rank_deficient_detected():
+    """Two copies of one grid alias degrees 0 and 2N together: rank deficient."""
+    S = W.total_degree_support(2, 6)
+    plan = O.build_plan(S, np.array([[3, 3], [3, 3]], dtype=np.int32))
+    assert not O.rank_check(plan)[0]
+    assert not O.fold_injective(S, [[3, 3], [3, 3]])
+
+
+def test_config2_instance_full_rank():
+    prob = W.config2()
+    assert prob.n == 18564 and prob.K == W.CFG2_MIN_GRIDS
+    assert prob.total_points >= 2 * prob.n
+    plan = O.build_plan(prob.support, prob.grids)
+    assert O.fold_injective(prob.support, prob.grids)
+    full, kappa = O.rank_check(plan)
+    assert full and kappa < 1e4
+
+
+@pytest.mark.slow
+def test_config2_normal_equations_match_qr_golden():
+    """The normal-equation route reproduces the stored QR minimiser."""
+    path = os.path.join(GOLDEN, "cfg2_coeffs_qr.npy")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    c_qr = np.load(path)
+    prob = W.config2()
+    c_ne, plan, b = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "normal")
+    assert O.max_rel_err(c_ne, c_qr) < 1e-11
+    with open(os.path.join(GOLDEN, "cfg2_meta.json")) as fh:
+        meta = json.load(fh)
+    assert meta["grids"] == prob.grids.tolist() and meta["M"] == plan.M
+
+
+def test_error_measures():
+    assert O.max_rel_err([1.0, 2.0], [1.0, 2.0]) == 0.0
+    assert abs(O.max_rel_err([1.0, 2.5], [1.0, 2.0]) - 0.25) < 1e-15
+    assert abs(O.mean_l2_err([3.0, 4.0], [0.0, 0.0]) - 2.5) < 1e-15
+
+
+def test_analytic_families_special_points():
+    """Values at the grid corner x = (1,..,1) and, for odd degrees, x = 0."""
+    D = 3
+    a = np.array([0.3, 0.5, 0.7]); w = np.array([0.6, 1.1, 1.9])
+    f1 = O.sample_function(1, np.concatenate([a, w]), [2, 2, 2])
+    # node (0,0,0) is x = (1,1,1); node (1,1,1) is x = (0,0,0)
+    assert abs(f1[0] - math.exp(-a.sum()) * math.cos(w.sum())) < 1e-15
+    assert abs(f1[1 * 9 + 1 * 3 + 1] - 1.0) < 1e-15
+    f3 = O.sample_function(3, [10.0], [2, 2, 2])
+    assert abs(f3[0] - 1 / 31) < 1e-15 and abs(f3[13] - 1.0) < 1e-15
+    f2 = O.sample_function(2, np.concatenate([[0.8], [0.1, 0.2, 0.3]]), [2, 2, 2])
+    assert abs(f2[13] - math.exp(-0.14 / 1.28)) < 1e-15
+    f4 = O.sample_function(4, [], [2, 2, 2])
+    assert abs(f4[13] - (math.sin(3 * math.cos(3.0)) + 1.0)) < 1e-14

@@ -1,0 +1,233 @@
+"""Seeded synthetic inputs for the sparse Fast Chebyshev Transform.
+
+This module is shared by the CPU oracle and by the GPU tests and benchmark.
+It produces *inputs only*: multi-index supports, grid resolutions, planted
+coefficient vectors and the parameters of analytic test functions.  It holds
+none of the transform's arithmetic (no Chebyshev evaluation, no aliasing, no
+DCT, no least squares), so that neither side can inherit a mistake from the
+other through it.
+
+Conventions (paper notation in brackets):
+
+* A support [the index set of nonzero coefficients, Sec. 2 and Sec. 4.5.3]
+  is an int32 array ``[n_support, D]`` in lexicographic ascending order.
+* A grid [one member of an L-grid, Sec. 3.2] is a row of D non-negative
+  ints ``N_i``: the Chebyshev-Lobatto *degree* along dimension i, i.e. the
+  grid has ``N_i + 1`` nodes ``cos(pi k / N_i)``; ``N_i = 0`` is the single
+  node ``x = 1``.  A stack of K grids is int32 ``[K, D]``.
+* Grid-point counts ``P = prod(N_i + 1)`` are plain counting, used only for
+  the oversampling stop rules of the workload recipes.
+
+Every generator takes an integer seed and derives independent streams with
+``numpy.random.SeedSequence(seed).spawn(3)`` -> (grid stream,
+coefficient/parameter stream, arrival stream).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "total_degree_support", "euclidean_degree_support", "grid_points",
+    "draw_grids_uniform", "draw_grid_capped", "planted_coefficients",
+    "Problem", "config1", "config2", "small_problem", "streams",
+    "FAMILY_PLANTED", "FAMILY_EXPCOS", "FAMILY_GAUSS", "FAMILY_RUNGE",
+    "FAMILY_OSC",
+]
+
+# Function-family identifiers (same integers as the C ABI's fct_family).
+FAMILY_PLANTED = 0   # f = sum_n c_n T_n(x) on the support (Sec. 4.5.1 recovery runs)
+FAMILY_EXPCOS = 1    # f = exp(-sum a_i x_i^2) cos(sum w_i x_i)
+FAMILY_GAUSS = 2     # f = exp(-|x - x0|^2 / (2 sigma^2))
+FAMILY_RUNGE = 3     # f1 of Sec. 4.3.1: 1 / (1 + alpha |x|^2)
+FAMILY_OSC = 4       # f2 of Sec. 4.3.2: sin(3 cos(3 exp|x|^2)) + exp(sin(3 sum x))
+
+
+def streams(seed: int):
+    """Three independent generators (grid, coefficient/parameter, arrival)."""
+    return [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(3)]
+
+
+def total_degree_support(D: int, d: int) -> np.ndarray:
+    """All n in N^D with |n|_1 <= d, lexicographic ascending (Sec. 2, S^1_{d,D}).
+
+    Built dimension by dimension: every partial row of the first i entries is
+    extended by each admissible value of entry i in increasing order, which
+    keeps the rows sorted lexicographically.
+    """
+    if D < 1 or d < 0:
+        raise ValueError("need D >= 1 and d >= 0")
+    rows = np.zeros((1, 0), dtype=np.int64)
+    used = np.zeros(1, dtype=np.int64)
+    for _ in range(D):
+        counts = d - used + 1
+        rep = np.repeat(np.arange(rows.shape[0]), counts)
+        starts = np.repeat(np.cumsum(counts) - counts, counts)
+        vals = np.arange(rep.size) - starts
+        rows = np.concatenate([rows[rep], vals[:, None]], axis=1)
+        used = used[rep] + vals
+    return np.ascontiguousarray(rows.astype(np.int32))
+
+
+def euclidean_degree_support(D: int, d: float) -> np.ndarray:
+    """All n in N^D with |n|_2 <= d, lexicographic ascending (Sec. 2, S^2_{d,D})."""
+    dmax = int(math.floor(d))
+    rows = np.zeros((1, 0), dtype=np.int64)
+    sq = np.zeros(1, dtype=np.int64)
+    lim = d * d + 1e-9
+    for _ in range(D):
+        rem = np.floor(np.sqrt(np.maximum(lim - sq, 0.0))).astype(np.int64)
+        rem = np.minimum(rem, dmax)
+        counts = rem + 1
+        rep = np.repeat(np.arange(rows.shape[0]), counts)
+        starts = np.repeat(np.cumsum(counts) - counts, counts)
+        vals = np.arange(rep.size) - starts
+        rows = np.concatenate([rows[rep], vals[:, None]], axis=1)
+        sq = sq[rep] + vals * vals
+        keep = sq <= lim
+        rows, sq = rows[keep], sq[keep]
+    return np.ascontiguousarray(rows.astype(np.int32))
+
+
+def grid_points(grid) -> int:
+    """Number of nodes of one tensor grid: prod(N_i + 1) (plain counting)."""
+    return int(np.prod(np.asarray(grid, dtype=np.int64) + 1))
+
+
+def draw_grids_uniform(rng, D, lo, hi, n_support, oversample, min_grids=1,
+                       max_grids=4096):
+    """i.i.d. ``N_i ~ U{lo..hi}`` grids, appended until the stacked point
+    count reaches ``oversample * n_support`` and at least ``min_grids`` grids
+    exist (the workload's floor that keeps the stacked system full rank)."""
+    grids, total = [], 0
+    while (total < oversample * n_support or len(grids) < min_grids):
+        g = rng.integers(lo, hi + 1, size=D)
+        grids.append(g)
+        total += grid_points(g)
+        if len(grids) >= max_grids:
+            break
+    return np.ascontiguousarray(np.array(grids, dtype=np.int32))
+
+
+def draw_grid_capped(rng, D, lo, hi, cap):
+    """One grid drawn the way the sampling-rate selection (Alg. 1) draws it.
+
+    Dimensions are visited in a random order; each gets a degree drawn from
+    ``U{lo..hi}``; once the running point count exceeds ``cap`` every
+    remaining dimension gets a single node (degree 0).  Degrees here are
+    Lobatto degrees, so the algorithm's draw of 1..d+1 *points* is a draw of
+    0..d here.
+    """
+    order = rng.permutation(D)
+    g = np.zeros(D, dtype=np.int64)
+    prod = 1
+    for i in order:
+        g[i] = rng.integers(lo, hi + 1)
+        prod *= int(g[i]) + 1
+        if prod > cap:
+            break
+    return g
+
+
+def draw_grids_capped(rng, D, lo, hi, n_support, oversample, min_grids=1,
+                      max_grids=4096):
+    grids, total = [], 0
+    while (total < oversample * n_support or len(grids) < min_grids):
+        g = draw_grid_capped(rng, D, lo, hi, n_support)
+        grids.append(g)
+        total += grid_points(g)
+        if len(grids) >= max_grids:
+            break
+    return np.ascontiguousarray(np.array(grids, dtype=np.int32))
+
+
+def planted_coefficients(rng, support) -> np.ndarray:
+    """c_n = z_n * 2^(-|n|_1/4), z ~ N(0,1): the planted-polynomial recipe."""
+    s = np.asarray(support, dtype=np.int64).sum(axis=1)
+    z = rng.standard_normal(len(support))
+    return z * np.exp2(-s / 4.0)
+
+
+@dataclass
+class Problem:
+    """One approximation job: support, grids and the function to sample."""
+    name: str
+    support: np.ndarray            # int32 [n, D]
+    grids: np.ndarray              # int32 [K, D]
+    family: int
+    params: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    coeffs: np.ndarray | None = None   # planted coefficients (FAMILY_PLANTED)
+    seed: int = 0
+
+    @property
+    def D(self):
+        return int(self.support.shape[1])
+
+    @property
+    def n(self):
+        return int(self.support.shape[0])
+
+    @property
+    def K(self):
+        return int(self.grids.shape[0])
+
+    @property
+    def points(self):
+        return [grid_points(g) for g in self.grids]
+
+    @property
+    def total_points(self):
+        return int(sum(self.points))
+
+
+def config1(seed: int = 0) -> Problem:
+    """D=2, |n|_1 <= 16 (153 coefficients), K=4 grids with N_i ~ U{9..24},
+    planted polynomial c_n ~ N(0,1) 2^(-|n|_1/4)."""
+    g_grid, g_coef, _ = streams(seed)
+    S = total_degree_support(2, 16)
+    grids = np.ascontiguousarray(g_grid.integers(9, 25, size=(4, 2)).astype(np.int32))
+    c = planted_coefficients(g_coef, S)
+    return Problem("cfg1_D2_d16_K4", S, grids, FAMILY_PLANTED, np.zeros(0), c, seed)
+
+
+# Grid floor for the D=6 workload: the 2x point-count stop rule alone stops
+# after one grid, which can never give a full-rank system.  Four grids is the
+# smallest count for which the seeded instance is full rank with
+# kappa(A) <= 1e4 (the stopping rule of Alg. 2), as the oracle's rank test
+# checks.
+CFG2_MIN_GRIDS = 4
+
+
+def config2(seed: int = 1, min_grids: int = CFG2_MIN_GRIDS) -> Problem:
+    """D=6, |n|_1 <= 12 (18,564 coefficients), grids N_i ~ U{4..8} appended
+    until the stacked points reach 2x the support size (and the grid floor),
+    f = exp(-sum a_i x_i^2) cos(sum w_i x_i), a_i ~ U(0.2,1), w_i ~ U(0.5,2)."""
+    g_grid, g_par, _ = streams(seed)
+    S = total_degree_support(6, 12)
+    grids = draw_grids_uniform(g_grid, 6, 4, 8, len(S), 2.0, min_grids)
+    a = g_par.uniform(0.2, 1.0, size=6)
+    w = g_par.uniform(0.5, 2.0, size=6)
+    return Problem("cfg2_D6_d12_expcos", S, grids, FAMILY_EXPCOS,
+                   np.concatenate([a, w]), None, seed)
+
+
+def small_problem(seed: int, D: int, d: int, lo: int, hi: int, K: int,
+                  family: int = FAMILY_PLANTED) -> Problem:
+    """A small total-degree problem with K i.i.d. U{lo..hi} grids."""
+    g_grid, g_coef, _ = streams(seed)
+    S = total_degree_support(D, d)
+    grids = np.ascontiguousarray(g_grid.integers(lo, hi + 1, size=(K, D)).astype(np.int32))
+    c = None
+    params = np.zeros(0)
+    if family == FAMILY_PLANTED:
+        c = planted_coefficients(g_coef, S)
+    elif family == FAMILY_EXPCOS:
+        params = np.concatenate([g_coef.uniform(0.2, 1.0, size=D),
+                                 g_coef.uniform(0.5, 2.0, size=D)])
+    elif family == FAMILY_GAUSS:
+        params = np.concatenate([[0.8], g_coef.uniform(-0.5, 0.5, size=D)])
+    elif family == FAMILY_RUNGE:
+        params = np.array([10.0])
+    return Problem(f"small_D{D}_d{d}_K{K}_s{seed}", S, grids, family, params, c, seed)
