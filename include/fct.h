@@ -1,0 +1,230 @@
+/*
+ * libfct: sparse Fast Chebyshev Transform on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the transform's hot path, after "A (Sparse) Fast Chebyshev
+ * Transform for High-Dimensional (Smooth Function) Approximation" (Jones,
+ * Letourneau, Morse, Langston; arXiv 2309.14584).  Given the known support
+ * of a function's Chebyshev expansion (the multi-indices of its nonzero
+ * coefficients, Sec. 4.5.3) and an L-grid of tensor Chebyshev grids
+ * (Sec. 3.2), the library
+ *
+ *   1. builds the alias structure of the stacked operator A (Sec. 3.1,
+ *      eq. aliasing_matrix_nd_diff; Alg. 2 without its conditioning loop),
+ *   2. samples f on every grid (Alg. 3, sampling step),
+ *   3. applies a separable D-dimensional DCT-I to every grid (Alg. 3,
+ *      transform step) and keeps the non-empty aliasing bins,
+ *   4. solves min_c || F f - A c ||_2 by CGLS (Alg. 3, least-squares step).
+ *
+ * Grids are Chebyshev-Lobatto grids: a grid is given by D Lobatto degrees
+ * N_i >= 0, with nodes x_k = cos(pi k / N_i), k = 0..N_i (N_i = 0 is the
+ * single node x = 1).  On such a grid T_n coincides with T_m,
+ * m = fold(n, N) = min(r, 2N - r), r = n mod 2N (the Lobatto analogue of
+ * Lemma 3.1), so every block A^(l) is 0/1 with exactly one 1 per column.
+ * The transform is the interpolation-normalised DCT-I
+ *   a_m = (g_m / N) [v_0 + (-1)^m v_N + 2 sum_{k=1}^{N-1} v_k cos(pi m k / N)],
+ *   g_0 = g_N = 1/2, g_m = 1 otherwise,
+ * which maps the samples of T_n to the unit vector of fold(n).
+ *
+ * Layouts (all row-major, "last dimension fastest"):
+ *   support   int32 [n_support][D], entries >= 0, no duplicate rows;
+ *   grids     int32 [K][D], Lobatto degrees 0 <= N_i <= FCT_MAX_DEGREE;
+ *   samples   double [P_total]: grid l's tensor of shape (N_1+1,...,N_D+1)
+ *             at offset point_offset(l), grids concatenated in order;
+ *   b         double [M]: the transform of grid l at its non-empty bins,
+ *             rows ordered by (grid ascending, flat bin ascending);
+ *   c         double [n_support] in support order.
+ *
+ * Conventions: every function returns an fct_status; on failure a message
+ * is available from fct_last_error() (per thread).  No call aborts the
+ * process.  Functions that take a stream enqueue their GPU work on it and
+ * return without waiting, except where stated.  Device pointers ("d_")
+ * are caller-owned device memory on the plan's device; the library never
+ * frees them.  A plan is immutable after creation and may be used from
+ * several streams at once; a workspace belongs to one stream at a time.
+ */
+#ifndef LIBFCT_FCT_H
+#define LIBFCT_FCT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCT_ABI_VERSION 1
+#define FCT_MAX_DIM 64       /* largest D accepted */
+#define FCT_MAX_DEGREE 63    /* largest Lobatto degree N_i (64 nodes) */
+
+typedef enum fct_status {
+  FCT_OK = 0,
+  FCT_EINVAL = 1,      /* invalid argument or unsupported size */
+  FCT_ENOMEM = 2,      /* device or host allocation failed */
+  FCT_EDEVICE = 3,     /* a HIP runtime call failed */
+  FCT_ERANK = 4,       /* the grids cannot separate the support (rank pre-check) */
+  FCT_ENOCONV = 5,     /* the solve stopped at its iteration limit */
+  FCT_ENONFINITE = 6   /* NaN or Inf met in the right-hand side */
+} fct_status;
+
+/* Function families understood by fct_sample. */
+typedef enum fct_family {
+  FCT_F_PLANTED = 0, /* p(x) = sum_j c_j T_{n_j}(x) on the support; params unused,
+                        d_coeffs = device double [n_support] */
+  FCT_F_EXPCOS = 1,  /* exp(-sum_i a_i x_i^2) cos(sum_i w_i x_i); params = a[D], w[D] */
+  FCT_F_GAUSS = 2,   /* exp(-|x - x0|^2 / (2 s^2)); params = s, x0[D] */
+  FCT_F_RUNGE = 3,   /* 1 / (1 + alpha |x|^2) (Sec. 4.3.1, f1); params = alpha */
+  FCT_F_OSC = 4      /* sin(3 cos(3 exp|x|^2)) + exp(sin(3 sum_i x_i)) (Sec. 4.3.2, f2) */
+} fct_family;
+
+/* Arithmetic of the DCT contractions. */
+typedef enum fct_dct_mode {
+  FCT_DCT_F64 = 0
+} fct_dct_mode;
+
+/* Arithmetic of the least-squares solve. */
+typedef enum fct_solve_mode {
+  FCT_SOLVE_F64 = 0  /* CGLS in FP64 throughout */
+} fct_solve_mode;
+
+/* Plan creation flags. */
+#define FCT_PLAN_ALLOW_RANK_DEFICIENT 1u /* skip the per-dimension rank pre-check */
+
+typedef struct fct_plan fct_plan;
+typedef struct fct_ws fct_ws;
+
+typedef struct fct_plan_info {
+  int32_t D;              /* dimension */
+  int32_t K;              /* number of grids */
+  int64_t n_support;      /* number of unknown coefficients */
+  int64_t total_points;   /* P_total = sum_l prod_i (N_i^(l) + 1) */
+  int64_t total_rows;     /* M = number of non-empty bins over all grids */
+  int64_t max_points;     /* largest single-grid point count */
+  int32_t max_degree;     /* largest N_i over all grids */
+  int32_t dct_levels;     /* kernel launches per DCT (axis-group passes) */
+  int64_t device_bytes;   /* device memory held by the plan */
+} fct_plan_info;
+
+typedef struct fct_solve_opts {
+  int32_t mode;         /* fct_solve_mode */
+  int32_t maxit;        /* iteration limit; 0 selects 4000 */
+  int32_t check_every;  /* iterations between host convergence checks; 0 selects 32 */
+  int32_t warm_start;   /* nonzero: d_c holds the starting guess, else start from 0 */
+  int32_t use_graph;    /* nonzero: replay the iteration chunk as a HIP graph */
+  int32_t reserved;
+  double tol;           /* stop when ||A^T r||_2 <= tol ||A^T r_0||_2; 0 selects 1e-14 */
+} fct_solve_opts;
+
+typedef struct fct_solve_info {
+  int32_t iterations;   /* CGLS iterations taken */
+  int32_t converged;    /* 1 if the tolerance was met */
+  double rel_normal_residual; /* ||A^T r_k||_2 / ||A^T r_0||_2 at exit */
+  double normal_residual0;    /* ||A^T r_0||_2 */
+} fct_solve_info;
+
+/* ---- errors ------------------------------------------------------------ */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* fct_last_error(void);
+/* Static name of a status code. */
+const char* fct_status_string(fct_status s);
+/* FCT_ABI_VERSION of the loaded library. */
+int32_t fct_abi_version(void);
+
+/* ---- plans (alias structure of A; Sec. 3.1-3.3, Alg. 2) ------------------
+ *
+ * fct_plan_create: copies the support and the grids to the current HIP
+ * device and builds, on the GPU, the alias structure of the stacked 0/1
+ * operator A = [A^(1); ...; A^(K)]:
+ *   alias[l][j]  flat bin of support row j on grid l:
+ *                sum_i fold(n_ji, N_i^(l)) * stride_i^(l), strides row-major;
+ *   perm[l][.]   support rows of grid l sorted by (bin, row) (stable);
+ *   seg_off[r]   start of row r's run in perm (flattened, K*n entries);
+ *   bin_id[r]    flat bin of row r;  rowmap[l][j] = global row of j on l.
+ * support and grids are host arrays read during the call only.  Unless
+ * flags has FCT_PLAN_ALLOW_RANK_DEFICIENT, the call fails with FCT_ERANK
+ * when some dimension i has two degrees a != a' <= max_j n_ji with
+ * fold(a, N_i^(l)) = fold(a', N_i^(l)) on every grid (two coefficients that
+ * differ only in entry i would then be indistinguishable).
+ * Limits (else FCT_EINVAL): 1 <= D <= FCT_MAX_DIM, n_support >= 1,
+ * 1 <= K < 2^19, K * n_support < 2^31, each grid's point count < 2^44,
+ * 0 <= N_i <= FCT_MAX_DEGREE, duplicate support rows rejected.
+ * Synchronous: waits for its work on `stream` before returning.
+ */
+fct_status fct_plan_create(int32_t D, int64_t n_support, const int32_t* support,
+                           int32_t K, const int32_t* grids, uint32_t flags,
+                           hipStream_t stream, fct_plan** out);
+void fct_plan_destroy(fct_plan* plan);
+fct_status fct_plan_get_info(const fct_plan* plan, fct_plan_info* out);
+/* Host query of grid l: point count, non-empty rows, offset of its tensor in
+ * the sample buffer and of its first row in b.  Any pointer may be NULL. */
+fct_status fct_plan_grid(const fct_plan* plan, int32_t grid, int64_t* points,
+                         int64_t* rows, int64_t* point_offset, int64_t* row_offset);
+/* Copy the alias structure into caller device buffers (any may be NULL):
+ * d_alias int64 [K*n], d_perm int32 [K*n], d_seg_off int32 [M+1],
+ * d_bin_id int64 [M], d_rowmap int32 [K*n].  Asynchronous on `stream`. */
+fct_status fct_plan_export(const fct_plan* plan, int64_t* d_alias, int32_t* d_perm,
+                           int32_t* d_seg_off, int64_t* d_bin_id, int32_t* d_rowmap,
+                           hipStream_t stream);
+/* Node coordinates of grid `grid` along dimension `dim` as used by the
+ * sampler: host_out[k] = cos(pi k / N), k = 0..N (synchronous). */
+fct_status fct_grid_nodes(const fct_plan* plan, int32_t grid, int32_t dim,
+                          double* host_out);
+
+/* ---- workspaces ---------------------------------------------------------
+ * Device scratch for one stream: the DCT intermediate tensor (P_total
+ * doubles) and the CGLS vectors and scalars.  Allocated on the plan's device.
+ */
+fct_status fct_ws_create(const fct_plan* plan, fct_ws** out);
+void fct_ws_destroy(fct_ws* ws);
+
+/* ---- sampling (Alg. 3: sample f on the L-grid) ---------------------------
+ * Writes f at every node of every grid into d_samples (double [P_total]).
+ * params: host array of n_params doubles as listed for fct_family.
+ * FCT_F_PLANTED evaluates p = sum_j c_j T_{n_j} by aliasing c onto each
+ * grid (q = A c) and applying the inverse DCT-I (evaluation at the nodes);
+ * it needs d_coeffs and a workspace.  Other families ignore d_coeffs and ws.
+ */
+fct_status fct_sample(const fct_plan* plan, int32_t family, const double* params,
+                      int32_t n_params, const double* d_coeffs, double* d_samples,
+                      fct_ws* ws, hipStream_t stream);
+
+/* ---- transform (Alg. 3: DCTs of every grid; eq. multi_dim_dct) ----------
+ * fct_dct: d_b[r] = (F^(l) f^(l))[bin_id[r]] for every non-empty row r,
+ * i.e. the separable interpolation-normalised DCT-I of each grid restricted
+ * to the bins that some support row aliases to.  d_samples double [P_total],
+ * d_b double [M].  mode: fct_dct_mode.
+ * fct_dct_full: the whole transformed tensors, d_out double [P_total].
+ */
+fct_status fct_dct(const fct_plan* plan, const double* d_samples, double* d_b,
+                   int32_t mode, fct_ws* ws, hipStream_t stream);
+fct_status fct_dct_full(const fct_plan* plan, const double* d_samples, double* d_out,
+                        int32_t mode, fct_ws* ws, hipStream_t stream);
+
+/* ---- operator (eq. main_linear_system) ----------------------------------
+ * fct_apply_A:  d_q[r] = sum over support rows j aliased to row r of d_c[j]
+ *               (double [n] -> double [M]); summed in perm order.
+ * fct_apply_AT: d_s[j] = sum_l d_r[rowmap[l][j]] (double [M] -> double [n]),
+ *               summed in grid order.  No atomics: results are reproducible.
+ */
+fct_status fct_apply_A(const fct_plan* plan, const double* d_c, double* d_q,
+                       hipStream_t stream);
+fct_status fct_apply_AT(const fct_plan* plan, const double* d_r, double* d_s,
+                        hipStream_t stream);
+
+/* ---- least squares (Sec. 3.4, Alg. 3: c* = argmin ||F f - A c||_2) -------
+ * CGLS on A c ~ b from c_0 = 0 (or the warm start in d_c).  Writes the
+ * iterate into d_c (double [n]).  Synchronous: waits on `stream` every
+ * opts->check_every iterations to test convergence, and at exit.
+ * opts may be NULL (defaults), info may be NULL.  Returns FCT_ENOCONV if
+ * maxit is reached first (d_c still holds the last iterate) and
+ * FCT_ENONFINITE if ||A^T b|| is not finite.
+ */
+fct_status fct_solve(const fct_plan* plan, const double* d_b, double* d_c,
+                     const fct_solve_opts* opts, fct_solve_info* info,
+                     fct_ws* ws, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBFCT_FCT_H */

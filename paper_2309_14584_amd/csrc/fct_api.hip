@@ -1,0 +1,653 @@
+// Host side of libfct: the C ABI, argument checks, plan construction,
+// DCT pass planning and the CGLS driver.  Every arithmetic step of the
+// transform runs in the kernels of the other source files.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "fct_internal.h"
+
+namespace fct {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+fct_status hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  return e == hipErrorOutOfMemory ? FCT_ENOMEM : FCT_EDEVICE;
+}
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, int64_t count, int64_t* bytes) {
+  const size_t sz = sizeof(T) * (size_t)(count > 0 ? count : 1);
+  hipError_t e = hipMalloc((void**)p, sz);
+  if (e == hipSuccess && bytes) *bytes += (int64_t)sz;
+  return e;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int64_t fold_host(int64_t a, int32_t N) {
+  if (N == 0) return 0;
+  const int64_t p = 2 * (int64_t)N;
+  const int64_t r = a % p;
+  return r < p - r ? r : p - r;
+}
+
+// One axis group of one grid: axes [first, last] (extents > 1 listed in ext).
+struct Group {
+  int first = 0, last = -1;
+  std::vector<int32_t> ext;
+  int64_t G = 1;
+};
+
+// Split grid axes into groups whose LDS tiles fit: the innermost group may
+// fill a whole tile (its tiles are contiguous runs of the tensor); the
+// other groups leave room for at least kOuterMinInner contiguous inner
+// elements per row.  Returned outermost first.
+std::vector<Group> make_groups(const int32_t* grid, int D) {
+  std::vector<Group> gs;
+  Group cur;
+  bool inner = true;
+  for (int i = D - 1; i >= 0; --i) {
+    const int32_t e = grid[i] + 1;
+    if (e == 1) continue;
+    const int64_t cap = inner ? kTileMax : kTileMax / kOuterMinInner;
+    if (!cur.ext.empty() && (cur.G * e > cap || (int)cur.ext.size() >= kMaxGroupAxes)) {
+      gs.push_back(cur);
+      cur = Group();
+      inner = false;
+    }
+    if (cur.ext.empty()) cur.last = i;
+    cur.first = i;
+    cur.ext.insert(cur.ext.begin(), e);
+    cur.G *= e;
+  }
+  if (!cur.ext.empty() || gs.empty()) {
+    if (cur.ext.empty()) { cur.first = 0; cur.last = -1; }
+    gs.push_back(cur);
+  }
+  std::reverse(gs.begin(), gs.end());
+  return gs;
+}
+
+PassDesc make_desc(const int32_t* grid, int D, const Group& g, int64_t point_off,
+                   int32_t row_begin, int32_t row_end, int32_t src, int32_t dst) {
+  PassDesc d;
+  std::memset(&d, 0, sizeof(d));
+  int64_t O = 1, I = 1;
+  if (g.last >= g.first) {
+    for (int i = 0; i < g.first; ++i) O *= grid[i] + 1;
+    for (int i = g.last + 1; i < D; ++i) I *= grid[i] + 1;
+  } else {
+    for (int i = 0; i < D; ++i) O *= grid[i] + 1;   // no axis to transform
+  }
+  d.O = O; d.G = g.G; d.I = I;
+  if (I == 1) {
+    d.TI = 1;
+    int64_t to = kTileMax / g.G;
+    if (to > O) to = O;
+    if (to < 1) to = 1;
+    d.TO = (int32_t)to;
+    d.tiles_i = 1;
+    d.ntiles = ceil_div(O, to);
+  } else {
+    d.TO = 1;
+    int64_t ti = kTileMax / g.G;
+    if (ti > I) ti = I;
+    if (ti < I && ti > kOuterMinInner) ti -= ti % kOuterMinInner;
+    d.TI = (int32_t)ti;
+    d.tiles_i = ceil_div(I, ti);
+    d.ntiles = O * d.tiles_i;
+  }
+  d.point_off = point_off;
+  d.row_begin = row_begin;
+  d.row_end = row_end;
+  d.naxes = (int32_t)g.ext.size();
+  for (int a = 0; a < d.naxes; ++a) d.ext[a] = g.ext[a];
+  d.src = src;
+  d.dst = dst;
+  return d;
+}
+
+// Upload one set of levels; descs[level] lists that level's passes.
+fct_status upload_levels(std::vector<std::vector<PassDesc>>& descs,
+                         std::vector<DctLevel>& out, int64_t* bytes) {
+  out.clear();
+  for (auto& lv : descs) {
+    DctLevel L;
+    int64_t tb = 0;
+    int32_t emax = 1;
+    for (auto& d : lv) {
+      d.tile_begin = tb;
+      tb += d.ntiles;
+      for (int a = 0; a < d.naxes; ++a) emax = std::max(emax, d.ext[a]);
+    }
+    if (tb > 0x7fffffffLL) {
+      set_error("DCT pass needs %lld workgroups (limit 2^31-1)", (long long)tb);
+      return FCT_EINVAL;
+    }
+    L.ndesc = (int32_t)lv.size();
+    L.tiles = tb;
+    L.emax = emax;
+    FCT_HIP(dalloc(&L.d_desc, (int64_t)lv.size(), bytes));
+    FCT_HIP(hipMemcpy(L.d_desc, lv.data(), sizeof(PassDesc) * lv.size(), hipMemcpyHostToDevice));
+    out.push_back(L);
+  }
+  return FCT_OK;
+}
+
+void free_levels(std::vector<DctLevel>& v) {
+  for (auto& L : v) dfree(L.d_desc);
+  v.clear();
+}
+
+void destroy_plan(fct_plan* p) {
+  if (!p) return;
+  dfree(p->d_support); dfree(p->d_grids); dfree(p->d_strides); dfree(p->d_point_off);
+  dfree(p->d_alias); dfree(p->d_perm); dfree(p->d_seg_off); dfree(p->d_bin_id);
+  dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_nodes); dfree(p->d_cmat);
+  dfree(p->d_emat);
+  free_levels(p->fwd);
+  free_levels(p->fwd_full);
+  free_levels(p->inv);
+  delete p;
+}
+
+fct_status build_dct_levels(fct_plan* p) {
+  const int K = p->K, D = p->D;
+  std::vector<std::vector<Group>> groups(K);
+  int maxlev = 0;
+  for (int l = 0; l < K; ++l) {
+    groups[l] = make_groups(&p->grids[(size_t)l * D], D);
+    maxlev = std::max(maxlev, (int)groups[l].size());
+  }
+  std::vector<std::vector<PassDesc>> fwd(maxlev), full(maxlev), inv(maxlev);
+  for (int l = 0; l < K; ++l) {
+    const int32_t* g = &p->grids[(size_t)l * D];
+    const auto& gs = groups[l];
+    const int np = (int)gs.size();
+    const int shift = maxlev - np;   // forward levels aligned at the end
+    for (int q = 0; q < np; ++q) {
+      const bool first = q == 0, last = q == np - 1;
+      fwd[shift + q].push_back(make_desc(g, D, gs[q], p->point_off[l], p->row_off[l],
+                                         p->row_off[l + 1], first ? kSrcInput : kSrcScratch,
+                                         last ? kDstGather : kDstScratch));
+      full[shift + q].push_back(make_desc(g, D, gs[q], p->point_off[l], p->row_off[l],
+                                          p->row_off[l + 1], first ? kSrcInput : kSrcOutput,
+                                          kDstOutput));
+      // inverse: innermost group first (level 0), scattering the row values
+      const int lev = np - 1 - q;
+      inv[lev].push_back(make_desc(g, D, gs[q], p->point_off[l], p->row_off[l],
+                                   p->row_off[l + 1], last ? kSrcRows : kSrcOutput,
+                                   kDstOutput));
+    }
+  }
+  fct_status st = upload_levels(fwd, p->fwd, &p->device_bytes);
+  if (st != FCT_OK) return st;
+  st = upload_levels(full, p->fwd_full, &p->device_bytes);
+  if (st != FCT_OK) return st;
+  return upload_levels(inv, p->inv, &p->device_bytes);
+}
+
+fct_status validate_inputs(int32_t D, int64_t n, const int32_t* S, int32_t K, const int32_t* G,
+                           uint32_t flags) {
+  if (D < 1 || D > FCT_MAX_DIM) { set_error("D=%d outside [1, %d]", D, FCT_MAX_DIM); return FCT_EINVAL; }
+  if (n < 1) { set_error("n_support must be >= 1"); return FCT_EINVAL; }
+  if (K < 1 || K >= (1 << 19)) { set_error("K=%d outside [1, 2^19)", K); return FCT_EINVAL; }
+  if (!S || !G) { set_error("support and grids must be non-NULL host arrays"); return FCT_EINVAL; }
+  if ((int64_t)K * n >= 0x7fffffffLL) { set_error("K * n_support must be < 2^31"); return FCT_EINVAL; }
+  for (int64_t t = 0; t < n * D; ++t)
+    if (S[t] < 0) { set_error("support entry %lld is negative", (long long)t); return FCT_EINVAL; }
+  for (int64_t l = 0; l < K; ++l) {
+    double pts = 1.0;
+    for (int i = 0; i < D; ++i) {
+      const int32_t N = G[l * D + i];
+      if (N < 0 || N > FCT_MAX_DEGREE) {
+        set_error("grid %lld dim %d: degree %d outside [0, %d]", (long long)l, i, N, FCT_MAX_DEGREE);
+        return FCT_EINVAL;
+      }
+      pts *= (double)(N + 1);
+    }
+    if (pts >= 17592186044416.0) {  // 2^44
+      set_error("grid %lld has %.3g points (limit 2^44)", (long long)l, pts);
+      return FCT_EINVAL;
+    }
+  }
+  // duplicate support rows
+  {
+    std::vector<int64_t> idx((size_t)n);
+    for (int64_t j = 0; j < n; ++j) idx[(size_t)j] = j;
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      return std::lexicographical_compare(S + a * D, S + a * D + D, S + b * D, S + b * D + D);
+    });
+    for (int64_t j = 1; j < n; ++j)
+      if (std::equal(S + idx[j] * D, S + idx[j] * D + D, S + idx[j - 1] * D)) {
+        set_error("support rows %lld and %lld are equal", (long long)idx[j - 1], (long long)idx[j]);
+        return FCT_EINVAL;
+      }
+  }
+  if (!(flags & FCT_PLAN_ALLOW_RANK_DEFICIENT)) {
+    // per dimension, the K folds must tell apart every degree that occurs
+    for (int i = 0; i < D; ++i) {
+      int32_t mx = 0;
+      for (int64_t j = 0; j < n; ++j) mx = std::max(mx, S[j * D + i]);
+      std::set<std::vector<int64_t>> seen;
+      for (int32_t a = 0; a <= mx; ++a) {
+        std::vector<int64_t> key((size_t)K);
+        for (int64_t l = 0; l < K; ++l) key[(size_t)l] = fold_host(a, G[l * D + i]);
+        if (!seen.insert(key).second) {
+          set_error("rank pre-check: dimension %d, degree %d aliases an earlier degree on "
+                    "every grid", i, a);
+          return FCT_ERANK;
+        }
+      }
+    }
+  }
+  return FCT_OK;
+}
+
+bool dev_ok(const fct_plan* p) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p->device) {
+    set_error("the current HIP device (%d) is not the plan's device (%d)", cur, p->device);
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+}  // namespace fct
+
+using namespace fct;
+
+extern "C" {
+
+const char* fct_last_error(void) { return g_last_error.c_str(); }
+
+const char* fct_status_string(fct_status s) {
+  switch (s) {
+    case FCT_OK: return "FCT_OK";
+    case FCT_EINVAL: return "FCT_EINVAL";
+    case FCT_ENOMEM: return "FCT_ENOMEM";
+    case FCT_EDEVICE: return "FCT_EDEVICE";
+    case FCT_ERANK: return "FCT_ERANK";
+    case FCT_ENOCONV: return "FCT_ENOCONV";
+    case FCT_ENONFINITE: return "FCT_ENONFINITE";
+  }
+  return "FCT_UNKNOWN";
+}
+
+int32_t fct_abi_version(void) { return FCT_ABI_VERSION; }
+
+fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t K,
+                           const int32_t* grids, uint32_t flags, hipStream_t stream,
+                           fct_plan** out) {
+  g_last_error.clear();
+  if (!out) { set_error("out is NULL"); return FCT_EINVAL; }
+  *out = nullptr;
+  fct_status st = validate_inputs(D, n, support, K, grids, flags);
+  if (st != FCT_OK) return st;
+
+  fct_plan* p = new (std::nothrow) fct_plan();
+  if (!p) { set_error("host allocation failed"); return FCT_ENOMEM; }
+  struct Guard {
+    fct_plan* p;
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    int32_t *v0 = nullptr, *v1 = nullptr, *bc = nullptr;
+    ~Guard() {
+      dfree(k0); dfree(k1); dfree(v0); dfree(v1); dfree(bc);
+      if (p) destroy_plan(p);
+    }
+  } guard{p};
+
+  FCT_HIP(hipGetDevice(&p->device));
+  p->D = D; p->K = K; p->n = n;
+  p->grids.assign(grids, grids + (size_t)K * D);
+  p->points.resize(K);
+  p->point_off.assign((size_t)K + 1, 0);
+  std::vector<int64_t> strides((size_t)K * D);
+  p->maxdeg = 0;
+  for (int l = 0; l < K; ++l) {
+    int64_t st_ = 1;
+    for (int i = D - 1; i >= 0; --i) {
+      strides[(size_t)l * D + i] = st_;
+      st_ *= grids[(size_t)l * D + i] + 1;
+      p->maxdeg = std::max(p->maxdeg, grids[(size_t)l * D + i]);
+    }
+    p->points[l] = st_;
+    p->point_off[l + 1] = p->point_off[l] + st_;
+    p->max_points = std::max(p->max_points, st_);
+  }
+  p->total_points = p->point_off[K];
+  const int64_t L = (int64_t)K * n;
+  int64_t* bytes = &p->device_bytes;
+
+  FCT_HIP(dalloc(&p->d_support, n * D, bytes));
+  FCT_HIP(dalloc(&p->d_grids, (int64_t)K * D, bytes));
+  FCT_HIP(dalloc(&p->d_strides, (int64_t)K * D, bytes));
+  FCT_HIP(dalloc(&p->d_point_off, (int64_t)K + 1, bytes));
+  FCT_HIP(dalloc(&p->d_alias, L, bytes));
+  FCT_HIP(dalloc(&p->d_perm, L, bytes));
+  FCT_HIP(dalloc(&p->d_seg_off, L + 1, bytes));
+  FCT_HIP(dalloc(&p->d_bin_id, L, bytes));
+  FCT_HIP(dalloc(&p->d_rowmap, L, bytes));
+  FCT_HIP(dalloc(&p->d_row_off, (int64_t)K + 1, bytes));
+  FCT_HIP(dalloc(&p->d_nodes, (int64_t)(p->maxdeg + 1) * 64, bytes));
+  FCT_HIP(dalloc(&p->d_cmat, mat_offset(p->maxdeg + 1), bytes));
+  FCT_HIP(dalloc(&p->d_emat, mat_offset(p->maxdeg + 1), bytes));
+  FCT_HIP(dalloc(&guard.k0, L, nullptr));
+  FCT_HIP(dalloc(&guard.k1, L, nullptr));
+  FCT_HIP(dalloc(&guard.v0, L, nullptr));
+  FCT_HIP(dalloc(&guard.v1, L, nullptr));
+  const int64_t nb = segment_blocks(L);
+  FCT_HIP(dalloc(&guard.bc, nb, nullptr));
+
+  FCT_HIP(hipMemcpyAsync(p->d_support, support, sizeof(int32_t) * n * D, hipMemcpyHostToDevice, stream));
+  FCT_HIP(hipMemcpyAsync(p->d_grids, grids, sizeof(int32_t) * K * D, hipMemcpyHostToDevice, stream));
+  FCT_HIP(hipMemcpyAsync(p->d_strides, strides.data(), sizeof(int64_t) * K * D, hipMemcpyHostToDevice, stream));
+  FCT_HIP(hipMemcpyAsync(p->d_point_off, p->point_off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, stream));
+
+  FCT_HIP(launch_tables(p->maxdeg, p->d_nodes, p->d_cmat, p->d_emat, stream));
+  FCT_HIP(launch_alias(p->d_support, p->d_grids, p->d_strides, D, n, K, p->d_alias, guard.k0,
+                       guard.v0, stream));
+  bool in_tmp = false;
+  FCT_HIP(launch_sort(guard.k0, guard.v0, guard.k1, guard.v1, L, &in_tmp, stream));
+  const uint64_t* ks = in_tmp ? guard.k1 : guard.k0;
+  const int32_t* vs = in_tmp ? guard.v1 : guard.v0;
+  FCT_HIP(launch_segments(ks, vs, L, n, guard.bc, nb, p->d_perm, p->d_seg_off, p->d_bin_id,
+                          p->d_rowmap, p->d_row_off, K, stream));
+  p->row_off.assign((size_t)K + 1, 0);
+  FCT_HIP(hipMemcpyAsync(p->row_off.data(), p->d_row_off, sizeof(int32_t) * (K + 1),
+                         hipMemcpyDeviceToHost, stream));
+  FCT_HIP(hipStreamSynchronize(stream));
+  p->M = p->row_off[K];
+
+  st = build_dct_levels(p);
+  if (st != FCT_OK) return st;
+  guard.p = nullptr;
+  *out = p;
+  return FCT_OK;
+}
+
+void fct_plan_destroy(fct_plan* plan) { destroy_plan(plan); }
+
+fct_status fct_plan_get_info(const fct_plan* p, fct_plan_info* o) {
+  if (!p || !o) { set_error("NULL argument"); return FCT_EINVAL; }
+  o->D = p->D; o->K = p->K; o->n_support = p->n; o->total_points = p->total_points;
+  o->total_rows = p->M; o->max_points = p->max_points; o->max_degree = p->maxdeg;
+  o->dct_levels = (int32_t)p->fwd.size(); o->device_bytes = p->device_bytes;
+  return FCT_OK;
+}
+
+fct_status fct_plan_grid(const fct_plan* p, int32_t l, int64_t* points, int64_t* rows,
+                         int64_t* point_offset, int64_t* row_offset) {
+  if (!p || l < 0 || l >= p->K) { set_error("bad plan or grid index"); return FCT_EINVAL; }
+  if (points) *points = p->points[l];
+  if (rows) *rows = p->row_off[l + 1] - p->row_off[l];
+  if (point_offset) *point_offset = p->point_off[l];
+  if (row_offset) *row_offset = p->row_off[l];
+  return FCT_OK;
+}
+
+fct_status fct_plan_export(const fct_plan* p, int64_t* d_alias, int32_t* d_perm,
+                           int32_t* d_seg_off, int64_t* d_bin_id, int32_t* d_rowmap,
+                           hipStream_t s) {
+  if (!p) { set_error("NULL plan"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  const int64_t L = (int64_t)p->K * p->n;
+  if (d_alias) FCT_HIP(hipMemcpyAsync(d_alias, p->d_alias, sizeof(int64_t) * L, hipMemcpyDeviceToDevice, s));
+  if (d_perm) FCT_HIP(hipMemcpyAsync(d_perm, p->d_perm, sizeof(int32_t) * L, hipMemcpyDeviceToDevice, s));
+  if (d_seg_off) FCT_HIP(hipMemcpyAsync(d_seg_off, p->d_seg_off, sizeof(int32_t) * (p->M + 1), hipMemcpyDeviceToDevice, s));
+  if (d_bin_id) FCT_HIP(hipMemcpyAsync(d_bin_id, p->d_bin_id, sizeof(int64_t) * p->M, hipMemcpyDeviceToDevice, s));
+  if (d_rowmap) FCT_HIP(hipMemcpyAsync(d_rowmap, p->d_rowmap, sizeof(int32_t) * L, hipMemcpyDeviceToDevice, s));
+  return FCT_OK;
+}
+
+fct_status fct_grid_nodes(const fct_plan* p, int32_t grid, int32_t dim, double* host_out) {
+  if (!p || !host_out || grid < 0 || grid >= p->K || dim < 0 || dim >= p->D) {
+    set_error("bad arguments");
+    return FCT_EINVAL;
+  }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  const int N = p->grids[(size_t)grid * p->D + dim];
+  FCT_HIP(hipMemcpy(host_out, p->d_nodes + (int64_t)N * 64, sizeof(double) * (N + 1),
+                    hipMemcpyDeviceToHost));
+  return FCT_OK;
+}
+
+fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
+  if (!p || !out) { set_error("NULL argument"); return FCT_EINVAL; }
+  *out = nullptr;
+  if (!dev_ok(p)) return FCT_EINVAL;
+  fct_ws* w = new (std::nothrow) fct_ws();
+  if (!w) { set_error("host allocation failed"); return FCT_ENOMEM; }
+  struct G { fct_ws* w; ~G() { if (w) fct_ws_destroy(w); } } guard{w};
+  w->device = p->device;
+  w->plan = p;
+  FCT_HIP(dalloc(&w->d_scratch, p->total_points, nullptr));
+  FCT_HIP(dalloc(&w->d_r, p->M, nullptr));
+  FCT_HIP(dalloc(&w->d_q, p->M, nullptr));
+  FCT_HIP(dalloc(&w->d_p, p->n, nullptr));
+  FCT_HIP(dalloc(&w->d_s, p->n, nullptr));
+  FCT_HIP(dalloc(&w->d_part_q, cgls_row_blocks(p->M), nullptr));
+  FCT_HIP(dalloc(&w->d_part_s, cgls_col_blocks(p->n), nullptr));
+  FCT_HIP(dalloc(&w->d_hist_gamma, kMaxHistory, nullptr));
+  FCT_HIP(dalloc(&w->d_hist_alpha, kMaxHistory, nullptr));
+  FCT_HIP(dalloc(&w->d_state, 4, nullptr));
+  FCT_HIP(hipHostMalloc((void**)&w->h_state, sizeof(int32_t) * 4, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_gamma, sizeof(double) * 2, hipHostMallocDefault));
+  FCT_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
+  guard.w = nullptr;
+  *out = w;
+  return FCT_OK;
+}
+
+void fct_ws_destroy(fct_ws* w) {
+  if (!w) return;
+  if (w->graph_exec) (void)hipGraphExecDestroy(w->graph_exec);
+  if (w->graph_stream) (void)hipStreamDestroy(w->graph_stream);
+  dfree(w->d_scratch); dfree(w->d_r); dfree(w->d_q); dfree(w->d_p); dfree(w->d_s);
+  dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_hist_gamma); dfree(w->d_hist_alpha);
+  dfree(w->d_state);
+  if (w->h_state) (void)hipHostFree(w->h_state);
+  if (w->h_gamma) (void)hipHostFree(w->h_gamma);
+  delete w;
+}
+
+static fct_status check_ws(const fct_plan* p, const fct_ws* w) {
+  if (!w) { set_error("this call needs a workspace"); return FCT_EINVAL; }
+  if (w->plan != p) { set_error("workspace was created for another plan"); return FCT_EINVAL; }
+  return FCT_OK;
+}
+
+fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, int32_t n_params,
+                      const double* d_coeffs, double* d_samples, fct_ws* ws, hipStream_t s) {
+  if (!p || !d_samples) { set_error("NULL plan or output"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  const int D = p->D;
+  if (family == FCT_F_PLANTED) {
+    if (!d_coeffs) { set_error("planted family needs d_coeffs"); return FCT_EINVAL; }
+    fct_status st = check_ws(p, ws);
+    if (st != FCT_OK) return st;
+    // q = A c at the non-empty bins, then evaluation at the nodes
+    FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_coeffs, ws->d_r, s));
+    for (const auto& lv : p->inv)
+      FCT_HIP(launch_dct_level(lv, ws->d_r, nullptr, d_samples, p->d_emat, p->d_bin_id, s));
+    return FCT_OK;
+  }
+  int need = 0;
+  switch (family) {
+    case FCT_F_EXPCOS: need = 2 * D; break;
+    case FCT_F_GAUSS: need = 1 + D; break;
+    case FCT_F_RUNGE: need = 1; break;
+    case FCT_F_OSC: need = 0; break;
+    default: set_error("unknown family %d", family); return FCT_EINVAL;
+  }
+  if (n_params < need || (need > 0 && !params)) {
+    set_error("family %d needs %d parameters, got %d", family, need, n_params);
+    return FCT_EINVAL;
+  }
+  SampleParams prm;
+  std::memset(&prm, 0, sizeof(prm));
+  for (int i = 0; i < need; ++i) prm.v[i] = params[i];
+  FCT_HIP(launch_sample(family, prm, D, p->K, p->d_grids, p->d_point_off, p->total_points,
+                               p->d_nodes, d_samples, s));
+  return FCT_OK;
+}
+
+static fct_status run_levels(const fct_plan* p, const std::vector<DctLevel>& levels,
+                             const double* in, double* out, int32_t mode, fct_ws* ws,
+                             hipStream_t s) {
+  if (mode != FCT_DCT_F64) { set_error("unsupported DCT mode %d", mode); return FCT_EINVAL; }
+  double* scratch = nullptr;
+  if (levels.size() > 1) {
+    fct_status st = check_ws(p, ws);
+    if (st != FCT_OK) return st;
+    scratch = ws->d_scratch;
+  }
+  for (const auto& lv : levels)
+    FCT_HIP(launch_dct_level(lv, in, scratch, out, p->d_cmat, p->d_bin_id, s));
+  return FCT_OK;
+}
+
+fct_status fct_dct(const fct_plan* p, const double* d_samples, double* d_b, int32_t mode,
+                   fct_ws* ws, hipStream_t s) {
+  if (!p || !d_samples || !d_b) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  return run_levels(p, p->fwd, d_samples, d_b, mode, ws, s);
+}
+
+fct_status fct_dct_full(const fct_plan* p, const double* d_samples, double* d_out, int32_t mode,
+                        fct_ws* ws, hipStream_t s) {
+  if (!p || !d_samples || !d_out) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  if (mode != FCT_DCT_F64) { set_error("unsupported DCT mode %d", mode); return FCT_EINVAL; }
+  for (const auto& lv : p->fwd_full)
+    FCT_HIP(launch_dct_level(lv, d_samples, nullptr, d_out, p->d_cmat, p->d_bin_id, s));
+  return FCT_OK;
+}
+
+fct_status fct_apply_A(const fct_plan* p, const double* d_c, double* d_q, hipStream_t s) {
+  if (!p || !d_c || !d_q) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_c, d_q, s));
+  return FCT_OK;
+}
+
+fct_status fct_apply_AT(const fct_plan* p, const double* d_r, double* d_s, hipStream_t s) {
+  if (!p || !d_r || !d_s) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  FCT_HIP(launch_apply_AT(p->d_rowmap, p->K, p->n, d_r, d_s, s));
+  return FCT_OK;
+}
+
+fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
+                     const fct_solve_opts* opts_in, fct_solve_info* info, fct_ws* ws,
+                     hipStream_t s) {
+  if (!p || !d_b || !d_c) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  fct_status st = check_ws(p, ws);
+  if (st != FCT_OK) return st;
+  fct_solve_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts_in) o = *opts_in;
+  if (o.mode != FCT_SOLVE_F64) { set_error("unsupported solve mode %d", o.mode); return FCT_EINVAL; }
+  if (o.maxit <= 0) o.maxit = 4000;
+  if (o.check_every <= 0) o.check_every = 32;
+  if (o.tol <= 0.0) o.tol = 1e-14;
+  if (o.check_every > 4096) o.check_every = 4096;
+  if ((int64_t)o.maxit + o.check_every + 2 > kMaxHistory) {
+    set_error("maxit %d too large (limit %d)", o.maxit, kMaxHistory - o.check_every - 2);
+    return FCT_EINVAL;
+  }
+  CglsArgs a;
+  a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.rowmap = p->d_rowmap;
+  a.M = p->M; a.n = p->n; a.K = p->K;
+  a.r = ws->d_r; a.q = ws->d_q; a.p = ws->d_p; a.s = ws->d_s; a.c = d_c;
+  a.part_q = ws->d_part_q; a.part_s = ws->d_part_s;
+  a.hist_gamma = ws->d_hist_gamma; a.hist_alpha = ws->d_hist_alpha;
+  a.state = ws->d_state; a.tol2 = o.tol * o.tol;
+
+  FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
+  const int chunk = o.check_every;
+  if (o.use_graph) {
+    const bool fresh = ws->graph_exec == nullptr || ws->graph_chunk != chunk ||
+                       ws->graph_c != d_c || ws->graph_tol2 != a.tol2;
+    if (fresh) {
+      if (ws->graph_exec) { (void)hipGraphExecDestroy(ws->graph_exec); ws->graph_exec = nullptr; }
+      hipGraph_t g = nullptr;
+      FCT_HIP(hipStreamBeginCapture(ws->graph_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int rel = 0; rel < chunk && e == hipSuccess; ++rel)
+        e = launch_cgls_iter(a, rel, ws->graph_stream);
+      if (e == hipSuccess) e = launch_cgls_advance(ws->d_state, chunk, ws->graph_stream);
+      hipError_t e2 = hipStreamEndCapture(ws->graph_stream, &g);
+      if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(e, "graph capture", __FILE__, __LINE__); }
+      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture", __FILE__, __LINE__);
+      e = hipGraphInstantiate(&ws->graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) { ws->graph_exec = nullptr; return hip_fail(e, "hipGraphInstantiate", __FILE__, __LINE__); }
+      ws->graph_chunk = chunk; ws->graph_c = d_c; ws->graph_tol2 = a.tol2;
+    }
+  }
+  int done_k = 0;
+  int32_t stop = 0, breakdown = 0;
+  while (done_k < o.maxit) {
+    const int c = std::min(chunk, o.maxit - done_k);
+    if (o.use_graph && c == chunk) {
+      FCT_HIP(hipGraphLaunch(ws->graph_exec, s));
+    } else {
+      for (int rel = 0; rel < c; ++rel) FCT_HIP(launch_cgls_iter(a, rel, s));
+      FCT_HIP(launch_cgls_advance(ws->d_state, c, s));
+    }
+    done_k += c;
+    FCT_HIP(hipMemcpyAsync(ws->h_state, ws->d_state, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipStreamSynchronize(s));
+    if (ws->h_state[0] != 0) { stop = ws->h_state[0]; breakdown = ws->h_state[2]; break; }
+  }
+  const int iters = stop ? stop - 1 : o.maxit;
+  if (!stop) FCT_HIP(launch_cgls_gamma(a, iters, s));
+  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[0], ws->d_hist_gamma, sizeof(double), hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[1], ws->d_hist_gamma + iters, sizeof(double), hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipStreamSynchronize(s));
+  const double g0 = ws->h_gamma[0], gk = ws->h_gamma[1];
+  const bool conv = stop && !breakdown;
+  if (info) {
+    info->iterations = iters;
+    info->converged = conv ? 1 : 0;
+    info->normal_residual0 = std::sqrt(g0);
+    info->rel_normal_residual = g0 > 0 ? std::sqrt(gk / g0) : 0.0;
+  }
+  if (!std::isfinite(g0)) { set_error("||A^T b|| is not finite"); return FCT_ENONFINITE; }
+  if (!conv && g0 > 0) {
+    set_error("CGLS stopped after %d iterations at relative normal residual %.3e%s", iters,
+              g0 > 0 ? std::sqrt(gk / g0) : 0.0, breakdown ? " (breakdown)" : "");
+    return FCT_ENOCONV;
+  }
+  return FCT_OK;
+}
+
+}  // extern "C"

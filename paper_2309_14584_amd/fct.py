@@ -1,0 +1,262 @@
+"""Python binding of libfct (ctypes).
+
+Argument marshalling only: every step of the transform runs in the HIP
+library.  Device buffers are PyTorch tensors on the current HIP device and
+work is enqueued on PyTorch's current stream.  Importing this module loads
+``libfct.so``; if it has not been built, the import fails with an error that
+says how to build it (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfct.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libfct is not built ({LIB_PATH} missing); build it with "
+        "`python -m paper_2309_14584_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes (include/fct.h)
+FCT_OK, FCT_EINVAL, FCT_ENOMEM, FCT_EDEVICE, FCT_ERANK, FCT_ENOCONV, FCT_ENONFINITE = range(7)
+FCT_PLAN_ALLOW_RANK_DEFICIENT = 1
+
+FAMILY_PLANTED, FAMILY_EXPCOS, FAMILY_GAUSS, FAMILY_RUNGE, FAMILY_OSC = range(5)
+DCT_F64 = 0
+SOLVE_F64 = 0
+
+_vp = ctypes.c_void_p
+_i32, _i64, _u32, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("D", _i32), ("K", _i32), ("n_support", _i64), ("total_points", _i64),
+                ("total_rows", _i64), ("max_points", _i64), ("max_degree", _i32),
+                ("dct_levels", _i32), ("device_bytes", _i64)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("maxit", _i32), ("check_every", _i32),
+                ("warm_start", _i32), ("use_graph", _i32), ("reserved", _i32),
+                ("tol", _dbl)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", _i32), ("converged", _i32),
+                ("rel_normal_residual", _dbl), ("normal_residual0", _dbl)]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_last_error = _sig("fct_last_error", ctypes.c_char_p)
+_status_string = _sig("fct_status_string", ctypes.c_char_p, ctypes.c_int)
+abi_version = _sig("fct_abi_version", _i32)
+_plan_create = _sig("fct_plan_create", ctypes.c_int, _i32, _i64, _vp, _i32, _vp, _u32, _vp,
+                    ctypes.POINTER(_vp))
+_plan_destroy = _sig("fct_plan_destroy", None, _vp)
+_plan_get_info = _sig("fct_plan_get_info", ctypes.c_int, _vp, ctypes.POINTER(PlanInfo))
+_plan_grid = _sig("fct_plan_grid", ctypes.c_int, _vp, _i32, ctypes.POINTER(_i64),
+                  ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64))
+_plan_export = _sig("fct_plan_export", ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_grid_nodes = _sig("fct_grid_nodes", ctypes.c_int, _vp, _i32, _i32, _vp)
+_ws_create = _sig("fct_ws_create", ctypes.c_int, _vp, ctypes.POINTER(_vp))
+_ws_destroy = _sig("fct_ws_destroy", None, _vp)
+_sample = _sig("fct_sample", ctypes.c_int, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp)
+_dct = _sig("fct_dct", ctypes.c_int, _vp, _vp, _vp, _i32, _vp, _vp)
+_dct_full = _sig("fct_dct_full", ctypes.c_int, _vp, _vp, _vp, _i32, _vp, _vp)
+_apply_A = _sig("fct_apply_A", ctypes.c_int, _vp, _vp, _vp, _vp)
+_apply_AT = _sig("fct_apply_AT", ctypes.c_int, _vp, _vp, _vp, _vp)
+_solve = _sig("fct_solve", ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
+              ctypes.POINTER(SolveInfo), _vp, _vp)
+
+EXPORTED = ["fct_last_error", "fct_status_string", "fct_abi_version", "fct_plan_create",
+            "fct_plan_destroy", "fct_plan_get_info", "fct_plan_grid", "fct_plan_export",
+            "fct_grid_nodes", "fct_ws_create", "fct_ws_destroy", "fct_sample", "fct_dct",
+            "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve"]
+
+
+class FctError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        super().__init__(f"{_status_string(status).decode()}: {msg}")
+
+
+def _check(status):
+    if status != FCT_OK:
+        raise FctError(status, _last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _ptr(t, dtype, numel, name):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return _vp(t.data_ptr())
+
+
+@dataclass
+class SolveResult:
+    iterations: int
+    converged: bool
+    rel_normal_residual: float
+    normal_residual0: float
+    status: int
+
+
+class Plan:
+    """Alias structure of a support on K Lobatto grids (fct_plan_create)."""
+
+    def __init__(self, support, grids, allow_rank_deficient=False, stream=None):
+        S = np.ascontiguousarray(np.asarray(support, dtype=np.int32))
+        G = np.ascontiguousarray(np.asarray(grids, dtype=np.int32))
+        if S.ndim != 2 or G.ndim != 2 or S.shape[1] != G.shape[1]:
+            raise ValueError("support [n, D] and grids [K, D] must share D")
+        self.support, self.grids = S, G
+        h = _vp()
+        flags = FCT_PLAN_ALLOW_RANK_DEFICIENT if allow_rank_deficient else 0
+        _check(_plan_create(S.shape[1], S.shape[0], S.ctypes.data_as(_vp), G.shape[0],
+                            G.ctypes.data_as(_vp), flags, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        info = PlanInfo()
+        _check(_plan_get_info(h, ctypes.byref(info)))
+        self.info = info
+        self.D, self.K, self.n = info.D, info.K, info.n_support
+        self.M, self.P = info.total_rows, info.total_points
+        self._ws = None
+
+    def close(self):
+        if self._ws is not None:
+            _ws_destroy(self._ws)
+            self._ws = None
+        if getattr(self, "_h", None):
+            _plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ws(self):
+        if self._ws is None:
+            w = _vp()
+            _check(_ws_create(self._h, ctypes.byref(w)))
+            self._ws = w
+        return self._ws
+
+    def grid(self, l):
+        vals = [_i64() for _ in range(4)]
+        _check(_plan_grid(self._h, l, *[ctypes.byref(v) for v in vals]))
+        return tuple(v.value for v in vals)   # points, rows, point_offset, row_offset
+
+    def nodes(self, l, i):
+        N = int(self.grids[l, i])
+        out = np.empty(N + 1)
+        _check(_grid_nodes(self._h, l, i, out.ctypes.data_as(_vp)))
+        return out
+
+    def export(self, stream=None):
+        torch = _torch()
+        L = self.K * self.n
+        dev = torch.device("cuda", torch.cuda.current_device())
+        alias = torch.empty(L, dtype=torch.int64, device=dev)
+        perm = torch.empty(L, dtype=torch.int32, device=dev)
+        seg = torch.empty(self.M + 1, dtype=torch.int32, device=dev)
+        bins = torch.empty(max(self.M, 1), dtype=torch.int64, device=dev)
+        rowmap = torch.empty(L, dtype=torch.int32, device=dev)
+        _check(_plan_export(self._h, _vp(alias.data_ptr()), _vp(perm.data_ptr()),
+                            _vp(seg.data_ptr()), _vp(bins.data_ptr()), _vp(rowmap.data_ptr()),
+                            _stream(stream)))
+        return dict(alias=alias.view(self.K, self.n), perm=perm.view(self.K, self.n),
+                    seg_off=seg, bin_id=bins[: self.M], rowmap=rowmap.view(self.K, self.n))
+
+    def _empty(self, n):
+        torch = _torch()
+        return torch.empty(max(int(n), 1), dtype=torch.float64,
+                           device=torch.device("cuda", torch.cuda.current_device()))[: int(n)]
+
+    def sample(self, family, params=(), coeffs=None, out=None, stream=None):
+        torch = _torch()
+        out = self._empty(self.P) if out is None else out
+        prm = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+        cptr = _ptr(coeffs, torch.float64, self.n, "coeffs")
+        _check(_sample(self._h, int(family), prm.ctypes.data_as(_vp) if prm.size else None,
+                       int(prm.size), cptr, _ptr(out, torch.float64, self.P, "out"),
+                       self.ws if family == FAMILY_PLANTED else None, _stream(stream)))
+        return out
+
+    def dct(self, samples, out=None, mode=DCT_F64, stream=None):
+        torch = _torch()
+        out = self._empty(self.M) if out is None else out
+        _check(_dct(self._h, _ptr(samples, torch.float64, self.P, "samples"),
+                    _ptr(out, torch.float64, self.M, "out"), mode, self.ws, _stream(stream)))
+        return out
+
+    def dct_full(self, samples, out=None, mode=DCT_F64, stream=None):
+        torch = _torch()
+        out = self._empty(self.P) if out is None else out
+        _check(_dct_full(self._h, _ptr(samples, torch.float64, self.P, "samples"),
+                         _ptr(out, torch.float64, self.P, "out"), mode, self.ws,
+                         _stream(stream)))
+        return out
+
+    def apply_A(self, c, out=None, stream=None):
+        torch = _torch()
+        out = self._empty(self.M) if out is None else out
+        _check(_apply_A(self._h, _ptr(c, torch.float64, self.n, "c"),
+                        _ptr(out, torch.float64, self.M, "out"), _stream(stream)))
+        return out
+
+    def apply_AT(self, r, out=None, stream=None):
+        torch = _torch()
+        out = self._empty(self.n) if out is None else out
+        _check(_apply_AT(self._h, _ptr(r, torch.float64, self.M, "r"),
+                         _ptr(out, torch.float64, self.n, "out"), _stream(stream)))
+        return out
+
+    def solve(self, b, out=None, tol=0.0, maxit=0, check_every=0, warm_start=False,
+              use_graph=True, mode=SOLVE_F64, raise_on_noconv=True, stream=None):
+        torch = _torch()
+        out = self._empty(self.n) if out is None else out
+        opts = SolveOpts(mode, int(maxit), int(check_every), 1 if warm_start else 0,
+                         1 if use_graph else 0, 0, float(tol))
+        info = SolveInfo()
+        st = _solve(self._h, _ptr(b, torch.float64, self.M, "b"),
+                    _ptr(out, torch.float64, self.n, "out"), ctypes.byref(opts),
+                    ctypes.byref(info), self.ws, _stream(stream))
+        if st != FCT_OK and (raise_on_noconv or st != FCT_ENOCONV):
+            _check(st)
+        return out, SolveResult(info.iterations, bool(info.converged),
+                                info.rel_normal_residual, info.normal_residual0, st)
