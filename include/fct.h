@@ -110,7 +110,10 @@ typedef struct fct_solve_opts {
   int32_t check_every;  /* iterations between host convergence checks; 0 selects 32 */
   int32_t warm_start;   /* nonzero: d_c holds the starting guess, else start from 0 */
   int32_t use_graph;    /* nonzero: replay the iteration chunk as a HIP graph */
-  int32_t reserved;
+  int32_t timing;       /* nonzero: after the solve, time 200 back-to-back launches of
+                           the row kernel and of the column kernel with HIP events on
+                           `stream` and report the means in fct_solve_info (d_c is
+                           left as solved) */
   double tol;           /* stop when ||A^T r||_2 <= tol ||A^T r_0||_2; 0 selects 1e-14 */
 } fct_solve_opts;
 
@@ -119,6 +122,8 @@ typedef struct fct_solve_info {
   int32_t converged;    /* 1 if the tolerance was met */
   double rel_normal_residual; /* ||A^T r_k||_2 / ||A^T r_0||_2 at exit */
   double normal_residual0;    /* ||A^T r_0||_2 */
+  double rows_kernel_us;      /* timing mode: mean time of one row-kernel launch (q = A p) */
+  double cols_kernel_us;      /* timing mode: mean time of one column-kernel launch (A^T r) */
 } fct_solve_info;
 
 /* ---- errors ------------------------------------------------------------ */
@@ -213,8 +218,10 @@ fct_status fct_apply_AT(const fct_plan* plan, const double* d_r, double* d_s,
 
 /* ---- least squares (Sec. 3.4, Alg. 3: c* = argmin ||F f - A c||_2) -------
  * CGLS on A c ~ b from c_0 = 0 (or the warm start in d_c).  Writes the
- * iterate into d_c (double [n]).  Synchronous: waits on `stream` every
- * opts->check_every iterations to test convergence, and at exit.
+ * iterate into d_c (double [n]).  Synchronous: iterations are enqueued in
+ * chunks of at most opts->check_every, two chunks deep; the host reads the
+ * convergence state of each chunk while the next one runs, and returns
+ * after the stream has drained.
  * opts may be NULL (defaults), info may be NULL.  Returns FCT_ENOCONV if
  * maxit is reached first (d_c still holds the last iterate) and
  * FCT_ENONFINITE if ||A^T b|| is not finite.

@@ -10,6 +10,12 @@
 // partials are summed in a fixed order by every consumer, so every run gives
 // the same bits.
 //
+// Layout: the row vectors r and q are interleaved as (r, q) pairs and the
+// column vectors p and s as (p, s) pairs, so each gather is one 16-byte load.
+// The row kernel reads a row's first entries from a 4-wide padded copy of
+// perm ("ell"), which saves the dependent load of the row's offset; longer
+// rows continue in perm.
+//
 // One CGLS iteration is two kernels.  With k the iteration number:
 //   rows_k: gamma_k = ||s_k||^2 (from the column partials), convergence test,
 //           beta_{k-1} = gamma_k / gamma_{k-1},
@@ -91,8 +97,7 @@ __global__ __launch_bounds__(kBlock) void cgls_init_rows_kernel(CglsArgs a,
     const int32_t t1 = a.seg_off[row + 1];
     for (int32_t t = a.seg_off[row]; t < t1; ++t) acc += a.c[a.perm[t]];
   }
-  a.r[row] = b[row] - acc;
-  a.q[row] = 0.0;
+  a.rq[row] = make_double2(b[row] - acc, 0.0);
 }
 
 // s_0 = A^T r_0, p = 0, c = 0 unless warm, partials of ||s_0||^2.
@@ -101,13 +106,24 @@ __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int 
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double sv = 0.0;
   if (j < a.n) {
-    for (int l = 0; l < a.K; ++l) sv += a.r[a.rowmap[(int64_t)l * a.n + j]];
-    a.s[j] = sv;
-    a.p[j] = 0.0;
+    for (int l = 0; l < a.K; ++l) sv += a.rq[a.rowmap[(int64_t)l * a.n + j]].x;
+    a.ps[j] = make_double2(0.0, sv);
     if (!warm) a.c[j] = 0.0;
   }
   const double part = block_sum(sv * sv, sh);
   if (threadIdx.x == 0) a.part_s[blockIdx.x] = part;
+}
+
+// Registers that prefetch a column's K aliases before the iteration scalars
+// are known; further grids continue in a loop.
+constexpr int kPrefetch = 4;
+
+// This thread's share of the other kernel's per-workgroup sums (loaded
+// before the state check so the loads overlap).
+__device__ __forceinline__ double load_partials(const double* __restrict__ part, int64_t np) {
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
+  return v;
 }
 
 __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel,
@@ -116,35 +132,55 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel,
   __shared__ int s_state[2];
   // one read per workgroup, so every wave of it takes the same branch
   if (threadIdx.x == 0) { s_state[0] = a.state[0]; s_state[1] = a.state[1]; }
+  const double gpart = load_partials(a.part_s, ncolblocks);
+  // operands that do not depend on this iteration's scalars
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = row < a.M;
+  double2 rq_old = make_double2(0.0, 0.0);
+  int4 e = make_int4(-1, -1, -1, -1);
+  if (active) {
+    rq_old = a.rq[row];
+    e = a.ell[row];
+  }
+  const double2 z = make_double2(0.0, 0.0);
+  const double2 v0 = e.x >= 0 ? a.ps[e.x] : z;
+  const double2 v1 = e.y >= 0 ? a.ps[e.y] : z;
+  const double2 v2 = e.z >= 0 ? a.ps[e.z] : z;
+  const double2 v3 = e.w >= 0 ? a.ps[e.w] : z;
   __syncthreads();
   if (s_state[0] != 0) return;                       // converged or stopped earlier
   const int k = s_state[1] + rel;
-  const double gamma = sum_partials(a.part_s, ncolblocks, sh);
-  double beta = 0.0, alpha_prev = 0.0;
+  double gprev = 1.0, g0 = 0.0, alpha_prev = 0.0;
+  if (k > 0) { gprev = a.hist_gamma[k - 1]; g0 = a.hist_gamma[0]; alpha_prev = a.hist_alpha[k - 1]; }
+  const double gamma = block_sum(gpart, sh);
+  double beta = 0.0;
   bool stop;
   if (k == 0) {
     stop = !(gamma > 0.0);                           // zero (or non-finite) A^T b
   } else {
-    const double gprev = a.hist_gamma[k - 1];
     beta = gamma / gprev;
-    alpha_prev = a.hist_alpha[k - 1];
-    stop = !(gamma > a.tol2 * a.hist_gamma[0]);
+    stop = !(gamma > a.tol2 * g0);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.hist_gamma[k] = gamma;
     if (stop) a.state[0] = k + 1;
   }
   if (stop) return;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double qv = 0.0;
-  if (row < a.M) {
-    a.r[row] = fma(-alpha_prev, a.q[row], a.r[row]);
-    const int32_t t1 = a.seg_off[row + 1];
-    for (int32_t t = a.seg_off[row]; t < t1; ++t) {
-      const int32_t j = a.perm[t];
-      qv += fma(beta, a.p[j], a.s[j]);
+  if (active) {
+    // terms in perm order: p_k = s_k + beta p_{k-1} for each aliased column
+    if (e.x >= 0) qv += fma(beta, v0.x, v0.y);
+    if (e.y >= 0) qv += fma(beta, v1.x, v1.y);
+    if (e.z >= 0) qv += fma(beta, v2.x, v2.y);
+    if (e.w >= 0) qv += fma(beta, v3.x, v3.y);
+    if (e.w < -1) {                                  // long row: rest of its run in perm
+      const int32_t t1 = a.seg_off[row + 1];
+      for (int32_t t = -(e.w + 2); t < t1; ++t) {
+        const double2 v = a.ps[a.perm[t]];
+        qv += fma(beta, v.x, v.y);
+      }
     }
-    a.q[row] = qv;
+    a.rq[row] = make_double2(fma(-alpha_prev, rq_old.y, rq_old.x), qv);
   }
   const double part = block_sum(qv * qv, sh);
   if (threadIdx.x == 0) a.part_q[blockIdx.x] = part;
@@ -155,29 +191,46 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel,
   __shared__ double sh[16];
   __shared__ int s_state[2];
   if (threadIdx.x == 0) { s_state[0] = a.state[0]; s_state[1] = a.state[1]; }
+  const double dpart = load_partials(a.part_q, nrowblocks);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = j < a.n;
+  double2 ps_old = make_double2(0.0, 0.0);
+  double c_old = 0.0;
+  double2 g[kPrefetch];
+  if (active) {
+    ps_old = a.ps[j];
+    c_old = a.c[j];
+  }
+#pragma unroll
+  for (int l = 0; l < kPrefetch; ++l) {
+    g[l] = make_double2(0.0, 0.0);
+    if (active && l < a.K) g[l] = a.rq[a.rowmap[(int64_t)l * a.n + j]];
+  }
   __syncthreads();
   if (s_state[0] != 0) return;
   const int k = s_state[1] + rel;
-  const double delta = sum_partials(a.part_q, nrowblocks, sh);
   const double gamma = a.hist_gamma[k];
-  const double beta = (k > 0) ? gamma / a.hist_gamma[k - 1] : 0.0;
+  const double gprev = (k > 0) ? a.hist_gamma[k - 1] : 1.0;
+  const double delta = block_sum(dpart, sh);
+  const double beta = (k > 0) ? gamma / gprev : 0.0;
   if (!(delta > 0.0)) {                              // A p = 0: breakdown
     if (blockIdx.x == 0 && threadIdx.x == 0) { a.state[2] = 1; a.state[0] = k + 1; }
     return;
   }
   const double alpha = gamma / delta;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.hist_alpha[k] = alpha;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double sv = 0.0;
-  if (j < a.n) {
-    const double pv = fma(beta, a.p[j], a.s[j]);
-    a.p[j] = pv;
-    a.c[j] = fma(alpha, pv, a.c[j]);
-    for (int l = 0; l < a.K; ++l) {
-      const int32_t row = a.rowmap[(int64_t)l * a.n + j];
-      sv += fma(-alpha, a.q[row], a.r[row]);
+  if (active) {
+    const double pv = fma(beta, ps_old.x, ps_old.y);
+    a.c[j] = fma(alpha, pv, c_old);
+#pragma unroll
+    for (int l = 0; l < kPrefetch; ++l)
+      if (l < a.K) sv += fma(-alpha, g[l].y, g[l].x);
+    for (int l = kPrefetch; l < a.K; ++l) {
+      const double2 v = a.rq[a.rowmap[(int64_t)l * a.n + j]];
+      sv += fma(-alpha, v.y, v.x);
     }
-    a.s[j] = sv;
+    a.ps[j] = make_double2(pv, sv);
   }
   const double part = block_sum(sv * sv, sh);
   if (threadIdx.x == 0) a.part_s[blockIdx.x] = part;
@@ -188,6 +241,10 @@ __global__ __launch_bounds__(kBlock) void cgls_gamma_kernel(CglsArgs a, int k,
   __shared__ double sh[16];
   const double gamma = sum_partials(a.part_s, ncolblocks, sh);
   if (threadIdx.x == 0) a.hist_gamma[k] = gamma;
+}
+
+__global__ void cgls_set_state_kernel(int32_t* state, int s0, int s1, int s2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) { state[0] = s0; state[1] = s1; state[2] = s2; }
 }
 
 __global__ void cgls_advance_kernel(int32_t* state, int chunk) {
@@ -223,17 +280,37 @@ hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s) {
-  const int64_t rb = cgls_row_blocks(a.M), cb = cgls_col_blocks(a.n);
-  hipLaunchKernelGGL(cgls_rows_kernel, dim3((unsigned)rb), dim3(kBlock), 0, s, a, rel, cb);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cgls_cols_kernel, dim3((unsigned)cb), dim3(kBlock), 0, s, a, rel, rb);
+hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s) {
+  hipLaunchKernelGGL(cgls_rows_kernel, dim3((unsigned)cgls_row_blocks(a.M)), dim3(kBlock), 0, s,
+                     a, rel, cgls_col_blocks(a.n));
   return hipGetLastError();
+}
+
+hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s) {
+  hipLaunchKernelGGL(cgls_cols_kernel, dim3((unsigned)cgls_col_blocks(a.n)), dim3(kBlock), 0, s,
+                     a, rel, cgls_row_blocks(a.M));
+  return hipGetLastError();
+}
+
+hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s) {
+  hipError_t e = launch_cgls_rows(a, rel, s);
+  if (e != hipSuccess) return e;
+  return launch_cgls_cols(a, rel, s);
 }
 
 hipError_t launch_cgls_gamma(const CglsArgs& a, int k, hipStream_t s) {
   hipLaunchKernelGGL(cgls_gamma_kernel, dim3(1), dim3(kBlock), 0, s, a, k, cgls_col_blocks(a.n));
+  return hipGetLastError();
+}
+
+hipError_t launch_cgls_timing_state(int32_t* state, int k, hipStream_t s) {
+  hipLaunchKernelGGL(cgls_set_state_kernel, dim3(1), dim3(64), 0, s, state, 0, k, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgls_timing_state_restore(int32_t* state, int stop, int breakdown,
+                                            hipStream_t s) {
+  hipLaunchKernelGGL(cgls_set_state_kernel, dim3(1), dim3(64), 0, s, state, stop, 0, breakdown);
   return hipGetLastError();
 }
 

@@ -29,6 +29,17 @@ __device__ __forceinline__ int64_t lower_bound_i64(const int64_t* __restrict__ a
   return lo;
 }
 
+constexpr int kUnroll = kTileMax / kBlock;   // tile elements per thread
+constexpr int kRowBatch = 8;                 // rows gathered / scattered per round
+
+// e / TI for 0 <= e < 2^24 (float quotient, then one exact correction).
+__device__ __forceinline__ int div_small(int e, int TI, float inv) {
+  int g = (int)((float)e * inv);
+  if (g * TI > e) --g;
+  else if ((g + 1) * TI <= e) ++g;
+  return g;
+}
+
 template <int EMAX>
 __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
     const PassDesc* __restrict__ descs, int ndesc, const double* __restrict__ in,
@@ -64,6 +75,9 @@ __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
   const int64_t flat_hi = (o0 + TOe) * G;
 
   // ---- load ----
+  // Every thread issues all of its global loads before it writes any of
+  // them to LDS, so their latencies overlap.
+  const float invTI = 1.0f / (float)TI;
   if (d.src == kSrcRows) {
     for (int e = threadIdx.x; e < nel; e += blockDim.x) tile[e] = 0.0;
     if (threadIdx.x == 0) {
@@ -71,19 +85,48 @@ __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
       s_rows[1] = lower_bound_i64(bin_id, d.row_begin, d.row_end, flat_hi);
     }
     __syncthreads();
-    for (int64_t r = s_rows[0] + threadIdx.x; r < s_rows[1]; r += blockDim.x)
-      tile[bin_id[r] - flat_lo] = in[r];
+    for (int64_t r0 = s_rows[0] + threadIdx.x; r0 < s_rows[1]; r0 += kRowBatch * blockDim.x) {
+      int64_t bb[kRowBatch];
+      double vv[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int64_t r = r0 + (int64_t)u * blockDim.x;
+        bb[u] = r < s_rows[1] ? bin_id[r] : -1;
+        vv[u] = r < s_rows[1] ? in[r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (bb[u] >= 0) tile[bb[u] - flat_lo] = vv[u];
+    }
   } else {
     const double* src = (d.src == kSrcInput) ? in : (d.src == kSrcOutput ? out : scratch);
     src += d.point_off;
-    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
-      const int i = e % TI;
-      const int rest = e / TI;
-      const int g = rest % (int)G;
-      const int o = rest / (int)G;
-      double v = 0.0;
-      if (o < TOe && i < TIe) v = src[(o0 + o) * G * I + (int64_t)g * I + i0 + i];
-      tile[e] = v;
+    double v[kUnroll];
+    if (I == 1) {                         // contiguous run of TOe * G elements
+      const int cnt = TOe * (int)G;
+      const double* base = src + flat_lo;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        v[u] = e < cnt ? base[e] : 0.0;
+      }
+    } else {                              // G rows of TI contiguous elements, stride I
+      const double* base = src + o0 * G * I + i0;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        v[u] = 0.0;
+        if (e < nel) {
+          const int g = div_small(e, TI, invTI);
+          const int i = e - g * TI;
+          if (i < TIe) v[u] = base[(int64_t)g * I + i];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      if (e < nel) tile[e] = v[u];
     }
   }
   __syncthreads();
@@ -128,16 +171,30 @@ __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
       s_rows[1] = lower_bound_i64(bin_id, d.row_begin, d.row_end, flat_hi);
     }
     __syncthreads();
-    for (int64_t r = s_rows[0] + threadIdx.x; r < s_rows[1]; r += blockDim.x)
-      out[r] = tile[bin_id[r] - flat_lo];
+    for (int64_t r0 = s_rows[0] + threadIdx.x; r0 < s_rows[1]; r0 += kRowBatch * blockDim.x) {
+      int64_t bb[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int64_t r = r0 + (int64_t)u * blockDim.x;
+        bb[u] = r < s_rows[1] ? bin_id[r] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (bb[u] >= 0) out[r0 + (int64_t)u * blockDim.x] = tile[bb[u] - flat_lo];
+    }
   } else {
     double* dst = ((d.dst == kDstOutput) ? out : scratch) + d.point_off;
-    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
-      const int i = e % TI;
-      const int rest = e / TI;
-      const int g = rest % (int)G;
-      const int o = rest / (int)G;
-      if (o < TOe && i < TIe) dst[(o0 + o) * G * I + (int64_t)g * I + i0 + i] = tile[e];
+    if (I == 1) {
+      const int cnt = TOe * (int)G;
+      double* base = dst + flat_lo;
+      for (int e = threadIdx.x; e < cnt; e += blockDim.x) base[e] = tile[e];
+    } else {
+      double* base = dst + o0 * G * I + i0;
+      for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const int g = div_small(e, TI, invTI);
+        const int i = e - g * TI;
+        if (i < TIe) base[(int64_t)g * I + i] = tile[e];
+      }
     }
   }
 }

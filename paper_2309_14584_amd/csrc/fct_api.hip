@@ -167,7 +167,7 @@ void destroy_plan(fct_plan* p) {
   if (!p) return;
   dfree(p->d_support); dfree(p->d_grids); dfree(p->d_strides); dfree(p->d_point_off);
   dfree(p->d_alias); dfree(p->d_perm); dfree(p->d_seg_off); dfree(p->d_bin_id);
-  dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_nodes); dfree(p->d_cmat);
+  dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_ell); dfree(p->d_nodes); dfree(p->d_cmat);
   dfree(p->d_emat);
   free_levels(p->fwd);
   free_levels(p->fwd_full);
@@ -384,6 +384,9 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
                          hipMemcpyDeviceToHost, stream));
   FCT_HIP(hipStreamSynchronize(stream));
   p->M = p->row_off[K];
+  FCT_HIP(dalloc(&p->d_ell, p->M, bytes));
+  FCT_HIP(launch_ell(p->d_seg_off, p->d_perm, p->M, p->d_ell, stream));
+  FCT_HIP(hipStreamSynchronize(stream));
 
   st = build_dct_levels(p);
   if (st != FCT_OK) return st;
@@ -448,17 +451,17 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   w->device = p->device;
   w->plan = p;
   FCT_HIP(dalloc(&w->d_scratch, p->total_points, nullptr));
-  FCT_HIP(dalloc(&w->d_r, p->M, nullptr));
-  FCT_HIP(dalloc(&w->d_q, p->M, nullptr));
-  FCT_HIP(dalloc(&w->d_p, p->n, nullptr));
-  FCT_HIP(dalloc(&w->d_s, p->n, nullptr));
+  FCT_HIP(dalloc(&w->d_rq, p->M, nullptr));
+  FCT_HIP(dalloc(&w->d_ps, p->n, nullptr));
+  FCT_HIP(dalloc(&w->d_ctmp, p->n, nullptr));
   FCT_HIP(dalloc(&w->d_part_q, cgls_row_blocks(p->M), nullptr));
   FCT_HIP(dalloc(&w->d_part_s, cgls_col_blocks(p->n), nullptr));
   FCT_HIP(dalloc(&w->d_hist_gamma, kMaxHistory, nullptr));
   FCT_HIP(dalloc(&w->d_hist_alpha, kMaxHistory, nullptr));
   FCT_HIP(dalloc(&w->d_state, 4, nullptr));
-  FCT_HIP(hipHostMalloc((void**)&w->h_state, sizeof(int32_t) * 4, hipHostMallocDefault));
-  FCT_HIP(hipHostMalloc((void**)&w->h_gamma, sizeof(double) * 2, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_state, sizeof(int32_t) * 8, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_gamma, sizeof(double) * 6, hipHostMallocDefault));
+  for (auto& e : w->ev) FCT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   FCT_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
   guard.w = nullptr;
   *out = w;
@@ -469,7 +472,8 @@ void fct_ws_destroy(fct_ws* w) {
   if (!w) return;
   if (w->graph_exec) (void)hipGraphExecDestroy(w->graph_exec);
   if (w->graph_stream) (void)hipStreamDestroy(w->graph_stream);
-  dfree(w->d_scratch); dfree(w->d_r); dfree(w->d_q); dfree(w->d_p); dfree(w->d_s);
+  for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
+  dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
   dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_hist_gamma); dfree(w->d_hist_alpha);
   dfree(w->d_state);
   if (w->h_state) (void)hipHostFree(w->h_state);
@@ -493,9 +497,10 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
     fct_status st = check_ws(p, ws);
     if (st != FCT_OK) return st;
     // q = A c at the non-empty bins, then evaluation at the nodes
-    FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_coeffs, ws->d_r, s));
+    double* q = reinterpret_cast<double*>(ws->d_rq);   // M doubles of scratch
+    FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_coeffs, q, s));
     for (const auto& lv : p->inv)
-      FCT_HIP(launch_dct_level(lv, ws->d_r, nullptr, d_samples, p->d_emat, p->d_bin_id, s));
+      FCT_HIP(launch_dct_level(lv, q, nullptr, d_samples, p->d_emat, p->d_bin_id, s));
     return FCT_OK;
   }
   int need = 0;
@@ -584,15 +589,16 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     return FCT_EINVAL;
   }
   CglsArgs a;
-  a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.rowmap = p->d_rowmap;
+  a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.ell = p->d_ell; a.rowmap = p->d_rowmap;
   a.M = p->M; a.n = p->n; a.K = p->K;
-  a.r = ws->d_r; a.q = ws->d_q; a.p = ws->d_p; a.s = ws->d_s; a.c = d_c;
+  a.rq = ws->d_rq; a.ps = ws->d_ps; a.c = d_c;
   a.part_q = ws->d_part_q; a.part_s = ws->d_part_s;
   a.hist_gamma = ws->d_hist_gamma; a.hist_alpha = ws->d_hist_alpha;
   a.state = ws->d_state; a.tol2 = o.tol * o.tol;
 
   FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
   const int chunk = o.check_every;
+  const bool timing = o.timing != 0;
   if (o.use_graph) {
     const bool fresh = ws->graph_exec == nullptr || ws->graph_chunk != chunk ||
                        ws->graph_c != d_c || ws->graph_tol2 != a.tol2;
@@ -613,29 +619,106 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
       ws->graph_chunk = chunk; ws->graph_c = d_c; ws->graph_tol2 = a.tol2;
     }
   }
-  int done_k = 0;
+
+  // Chunks of iterations are kept two deep in the stream: while chunk i
+  // runs, the host reads the convergence state copied after chunk i-1.
+  // From the observed decrease of ||A^T r||^2 the host predicts how many
+  // iterations remain and shortens the next chunk accordingly, so few
+  // (early-exiting) launches run after convergence.
+  struct Slot { int upto; };
+  Slot slots[2];
+  int head = 0, inflight = 0, queued = 0;
   int32_t stop = 0, breakdown = 0;
-  while (done_k < o.maxit) {
-    const int c = std::min(chunk, o.maxit - done_k);
-    if (o.use_graph && c == chunk) {
-      FCT_HIP(hipGraphLaunch(ws->graph_exec, s));
-    } else {
-      for (int rel = 0; rel < c; ++rel) FCT_HIP(launch_cgls_iter(a, rel, s));
-      FCT_HIP(launch_cgls_advance(ws->d_state, c, s));
+  int kprev = -1, klast = -1;
+  double gprev = 0.0, glast = 0.0, g0seen = -1.0;
+  int target = o.maxit;
+  while (true) {
+    while (inflight < 2 && queued < o.maxit && queued < target) {
+      int c = std::min(chunk, std::min(o.maxit, target) - queued);
+      if (c < 1) c = 1;
+      if (o.use_graph && c == chunk) {
+        FCT_HIP(hipGraphLaunch(ws->graph_exec, s));
+      } else {
+        for (int rel = 0; rel < c; ++rel) FCT_HIP(launch_cgls_iter(a, rel, s));
+        FCT_HIP(launch_cgls_advance(ws->d_state, c, s));
+      }
+      queued += c;
+      const int sl = (head + inflight) & 1;
+      slots[sl].upto = queued;
+      FCT_HIP(hipMemcpyAsync(ws->h_state + 4 * sl, ws->d_state, sizeof(int32_t) * 4,
+                             hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipMemcpyAsync(ws->h_gamma + 2 * sl, ws->d_hist_gamma + (queued - 1),
+                             sizeof(double), hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipMemcpyAsync(ws->h_gamma + 2 * sl + 1, ws->d_hist_gamma, sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipEventRecord(ws->ev[sl], s));
+      ++inflight;
     }
-    done_k += c;
-    FCT_HIP(hipMemcpyAsync(ws->h_state, ws->d_state, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
-    FCT_HIP(hipStreamSynchronize(s));
-    if (ws->h_state[0] != 0) { stop = ws->h_state[0]; breakdown = ws->h_state[2]; break; }
+    if (inflight == 0) break;
+    const int sl = head;
+    FCT_HIP(hipEventSynchronize(ws->ev[sl]));
+    head ^= 1;
+    --inflight;
+    const int32_t* hs = ws->h_state + 4 * sl;
+    if (hs[0] != 0) { stop = hs[0]; breakdown = hs[2]; break; }
+    // rate estimate of ||A^T r_k||^2 and the iterations still needed
+    kprev = klast; gprev = glast;
+    klast = slots[sl].upto - 1;
+    glast = ws->h_gamma[2 * sl];
+    g0seen = ws->h_gamma[2 * sl + 1];
+    if (kprev >= 0 && glast > 0.0 && gprev > glast && g0seen > 0.0) {
+      const double lrate = (std::log(glast) - std::log(gprev)) / (double)(klast - kprev);
+      const double need = (std::log(a.tol2 * g0seen) - std::log(glast)) / lrate;
+      if (std::isfinite(need) && need >= 0.0) {
+        const double t = (double)klast + need + 2.0;
+        target = t < (double)o.maxit ? (int)t + 1 : o.maxit;
+        if (target <= queued) target = queued + 1;   // keep going one at a time
+      }
+    }
+    if (queued >= target && inflight == 0 && queued < o.maxit) target = queued + 1;
   }
+  FCT_HIP(hipStreamSynchronize(s));
   const int iters = stop ? stop - 1 : o.maxit;
   if (!stop) FCT_HIP(launch_cgls_gamma(a, iters, s));
-  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[0], ws->d_hist_gamma, sizeof(double), hipMemcpyDeviceToHost, s));
-  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[1], ws->d_hist_gamma + iters, sizeof(double), hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[4], ws->d_hist_gamma, sizeof(double), hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[5], ws->d_hist_gamma + iters, sizeof(double), hipMemcpyDeviceToHost, s));
   FCT_HIP(hipStreamSynchronize(s));
-  const double g0 = ws->h_gamma[0], gk = ws->h_gamma[1];
+  const double g0 = ws->h_gamma[4], gk = ws->h_gamma[5];
+  if (timing && iters > 0) {
+    // Mean kernel times from back-to-back launches bracketed by HIP events
+    // on this stream, after the solve: the row kernel re-runs iteration
+    // iters-1 with the stop test disabled (it only rewrites r, q, the row
+    // partials and that iteration's history entry), then the column kernel
+    // runs with its coefficient
+    // update directed into scratch, so d_c keeps the solution.
+    constexpr int kReps = 200;
+    CglsArgs t = a;
+    t.tol2 = 0.0;
+    t.c = ws->d_ctmp;
+    const int kt = iters - 1;
+    hipEvent_t ev[3];
+    for (auto& e : ev) FCT_HIP(hipEventCreate(&e));
+    struct EG { hipEvent_t* e; ~EG() { for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]); } } eg{ev};
+    FCT_HIP(launch_cgls_timing_state(ws->d_state, kt, s));
+    FCT_HIP(hipEventRecord(ev[0], s));
+    for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_rows(t, 0, s));
+    FCT_HIP(hipEventRecord(ev[1], s));
+    for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_cols(t, 0, s));
+    FCT_HIP(hipEventRecord(ev[2], s));
+    FCT_HIP(hipEventSynchronize(ev[2]));
+    float m1 = 0.f, m2 = 0.f;
+    FCT_HIP(hipEventElapsedTime(&m1, ev[0], ev[1]));
+    FCT_HIP(hipEventElapsedTime(&m2, ev[1], ev[2]));
+    if (info) {
+      info->rows_kernel_us = 1e3 * m1 / kReps;
+      info->cols_kernel_us = 1e3 * m2 / kReps;
+    }
+    FCT_HIP(launch_cgls_timing_state_restore(ws->d_state, stop, breakdown, s));
+    FCT_HIP(hipStreamSynchronize(s));
+  }
   const bool conv = stop && !breakdown;
   if (info) {
+    if (!timing) { info->rows_kernel_us = 0.0; info->cols_kernel_us = 0.0; }
     info->iterations = iters;
     info->converged = conv ? 1 : 0;
     info->normal_residual0 = std::sqrt(g0);

@@ -80,6 +80,11 @@ hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
                            int32_t* rowmap, int32_t* row_off, int K, hipStream_t s);
 hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, double* emat,
                          hipStream_t s);
+// ell[r] = first four entries of row r's run in perm, -1 padded; a row with
+// more than four entries stores -(2 + t) in the last slot, t = perm index
+// where its remaining entries continue
+hipError_t launch_ell(const int32_t* seg_off, const int32_t* perm, int64_t M, int4* ell,
+                      hipStream_t s);
 
 // DCT passes
 hipError_t launch_dct_level(const DctLevel& lv, const double* in, double* scratch,
@@ -105,13 +110,12 @@ hipError_t launch_apply_AT(const int32_t* rowmap, int K, int64_t n, const double
 struct CglsArgs {
   const int32_t* seg_off;
   const int32_t* perm;
+  const int4* ell;    // [M] first four columns of each row (see plan)
   const int32_t* rowmap;
   int64_t M, n;
   int32_t K;
-  double* r;          // [M]
-  double* q;          // [M]
-  double* p;          // [n]
-  double* s;          // [n]
+  double2* rq;        // [M] (r, q) per row
+  double2* ps;        // [n] (p, s) per column
   double* c;          // [n]
   double* part_q;     // [nblocks rows]
   double* part_s;     // [nblocks cols]
@@ -122,9 +126,15 @@ struct CglsArgs {
 };
 hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipStream_t s);
 hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s);
+hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s);
+hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s);
 hipError_t launch_cgls_advance(int32_t* state, int chunk, hipStream_t s);
 // hist_gamma[k] = ||s||^2 from the current column partials
 hipError_t launch_cgls_gamma(const CglsArgs& a, int k, hipStream_t s);
+// timing support: state = (running, base k); then back to the recorded stop
+hipError_t launch_cgls_timing_state(int32_t* state, int k, hipStream_t s);
+hipError_t launch_cgls_timing_state_restore(int32_t* state, int stop, int breakdown,
+                                            hipStream_t s);
 int64_t segment_blocks(int64_t L);
 int64_t cgls_row_blocks(int64_t M);
 int64_t cgls_col_blocks(int64_t n);
@@ -156,6 +166,7 @@ struct fct_plan {
   int64_t* d_bin_id = nullptr;     // [M]
   int32_t* d_rowmap = nullptr;     // [K*n]
   int32_t* d_row_off = nullptr;    // [K+1]
+  int4* d_ell = nullptr;           // [M]
   double* d_nodes = nullptr;       // [(maxdeg+1) * 64]
   double* d_cmat = nullptr;        // packed forward DCT-I matrices, degrees 0..maxdeg
   double* d_emat = nullptr;        // packed evaluation matrices
@@ -169,18 +180,18 @@ struct fct_ws {
   int device = 0;
   const fct_plan* plan = nullptr;
   double* d_scratch = nullptr;     // [total_points]
-  double* d_r = nullptr;           // [M]
-  double* d_q = nullptr;           // [M]
-  double* d_p = nullptr;           // [n]
-  double* d_s = nullptr;           // [n]
+  double2* d_rq = nullptr;         // [M]
+  double2* d_ps = nullptr;         // [n]
+  double* d_ctmp = nullptr;        // [n] coefficient sink of timing launches
   double* d_part_q = nullptr;
   double* d_part_s = nullptr;
   double* d_hist_gamma = nullptr;
   double* d_hist_alpha = nullptr;
   double* d_params = nullptr;      // [2 * FCT_MAX_DIM + 8] sampler parameters
   int32_t* d_state = nullptr;      // [4]
-  int32_t* h_state = nullptr;      // pinned [4]
-  double* h_gamma = nullptr;       // pinned [2]
+  int32_t* h_state = nullptr;      // pinned [2][4]: state copies of two in-flight chunks
+  double* h_gamma = nullptr;       // pinned [6]: per chunk (gamma_last, gamma_0), then final pair
+  hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;
   int graph_chunk = 0;

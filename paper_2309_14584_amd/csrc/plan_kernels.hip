@@ -250,7 +250,29 @@ __global__ __launch_bounds__(kBlock) void tables_kernel(int maxdeg, double* __re
   emat[t] = cs;
 }
 
+__global__ __launch_bounds__(kBlock) void ell_kernel(const int32_t* __restrict__ seg_off,
+                                                     const int32_t* __restrict__ perm, int64_t M,
+                                                     int4* __restrict__ ell) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= M) return;
+  const int32_t t0 = seg_off[r], t1 = seg_off[r + 1];
+  const int32_t len = t1 - t0;
+  int4 e;
+  e.x = len > 0 ? perm[t0] : -1;
+  e.y = len > 1 ? perm[t0 + 1] : -1;
+  e.z = len > 2 ? perm[t0 + 2] : -1;
+  e.w = len == 4 ? perm[t0 + 3] : (len > 4 ? -(2 + (t0 + 3)) : -1);
+  ell[r] = e;
+}
+
 }  // namespace
+
+hipError_t launch_ell(const int32_t* seg_off, const int32_t* perm, int64_t M, int4* ell,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(ell_kernel, dim3((unsigned)ceil_div(M, kBlock)), dim3(kBlock), 0, s, seg_off,
+                     perm, M, ell);
+  return hipGetLastError();
+}
 
 hipError_t launch_alias(const int32_t* S, const int32_t* grids, const int64_t* strides,
                         int D, int64_t n, int K, int64_t* alias, uint64_t* keys,

@@ -44,13 +44,14 @@ class PlanInfo(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("mode", _i32), ("maxit", _i32), ("check_every", _i32),
-                ("warm_start", _i32), ("use_graph", _i32), ("reserved", _i32),
+                ("warm_start", _i32), ("use_graph", _i32), ("timing", _i32),
                 ("tol", _dbl)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32),
-                ("rel_normal_residual", _dbl), ("normal_residual0", _dbl)]
+                ("rel_normal_residual", _dbl), ("normal_residual0", _dbl),
+                ("rows_kernel_us", _dbl), ("cols_kernel_us", _dbl)]
 
 
 def _sig(name, res, *args):
@@ -131,6 +132,8 @@ class SolveResult:
     rel_normal_residual: float
     normal_residual0: float
     status: int
+    rows_kernel_us: float = 0.0
+    cols_kernel_us: float = 0.0
 
 
 class Plan:
@@ -247,11 +250,12 @@ class Plan:
         return out
 
     def solve(self, b, out=None, tol=0.0, maxit=0, check_every=0, warm_start=False,
-              use_graph=True, mode=SOLVE_F64, raise_on_noconv=True, stream=None):
+              use_graph=True, mode=SOLVE_F64, raise_on_noconv=True, timing=False,
+              stream=None):
         torch = _torch()
         out = self._empty(self.n) if out is None else out
         opts = SolveOpts(mode, int(maxit), int(check_every), 1 if warm_start else 0,
-                         1 if use_graph else 0, 0, float(tol))
+                         1 if use_graph else 0, 1 if timing else 0, float(tol))
         info = SolveInfo()
         st = _solve(self._h, _ptr(b, torch.float64, self.M, "b"),
                     _ptr(out, torch.float64, self.n, "out"), ctypes.byref(opts),
@@ -259,4 +263,5 @@ class Plan:
         if st != FCT_OK and (raise_on_noconv or st != FCT_ENOCONV):
             _check(st)
         return out, SolveResult(info.iterations, bool(info.converged),
-                                info.rel_normal_residual, info.normal_residual0, st)
+                                info.rel_normal_residual, info.normal_residual0, st,
+                                info.rows_kernel_us, info.cols_kernel_us)

@@ -1,0 +1,28 @@
+"""Host-side checks of bench.py's contract (no GPU)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_profile_record_parses():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    text = open(b.PROFILE).read()
+    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    assert rec["kernel"] == "cgls_rows_kernel" and rec["traffic_bytes_per_launch"] > 0
+
+    class P:
+        M, n, K = 55008, 18564, 4
+    # 32 M + 4 (M + 1) + 20 K n + 8 (rb + cb) for the D=6 workload
+    assert b.rows_kernel_bytes(P) == 3467716

@@ -94,7 +94,8 @@ def test_nodes(fct, prob):
     for l in range(prob.K):
         for i in range(prob.D):
             ref = O.lobatto_nodes(int(prob.grids[l, i]))
-            assert np.max(np.abs(plan.nodes(l, i) - ref)) < 4e-16
+            # the oracle rounds pi*k/N before its cosine; a few ulp apart
+            assert np.max(np.abs(plan.nodes(l, i) - ref)) < 1e-15
     plan.close()
 
 
