@@ -76,9 +76,14 @@ typedef enum fct_family {
   FCT_F_OSC = 4      /* sin(3 cos(3 exp|x|^2)) + exp(sin(3 sum_i x_i)) (Sec. 4.3.2, f2) */
 } fct_family;
 
-/* Arithmetic of the DCT contractions. */
+/* Arithmetic of the DCT contractions (all on the matrix cores for extents
+ * up to 32; larger extents use FP64 vector FMAs and accept FCT_DCT_F64 only). */
 typedef enum fct_dct_mode {
-  FCT_DCT_F64 = 0
+  FCT_DCT_F64 = 0,    /* FP64 products and sums, FP64 intermediate tensors */
+  FCT_DCT_F32 = 1,    /* FP32 products and sums, FP32 intermediate tensors */
+  FCT_DCT_BF16X3 = 2  /* operands split into bf16 high/low parts (round to nearest
+                         even); C_hi x_hi + C_hi x_lo + C_lo x_hi with FP32
+                         accumulation; FP32 intermediate tensors */
 } fct_dct_mode;
 
 /* Arithmetic of the least-squares solve. */
@@ -102,6 +107,8 @@ typedef struct fct_plan_info {
   int32_t max_degree;     /* largest N_i over all grids */
   int32_t dct_levels;     /* kernel launches per DCT (axis-group passes) */
   int64_t device_bytes;   /* device memory held by the plan */
+  int32_t problems;       /* 1, or the number of problems of a batch plan */
+  int32_t reserved;
 } fct_plan_info;
 
 typedef struct fct_solve_opts {
@@ -118,12 +125,14 @@ typedef struct fct_solve_opts {
 } fct_solve_opts;
 
 typedef struct fct_solve_info {
-  int32_t iterations;   /* CGLS iterations taken */
-  int32_t converged;    /* 1 if the tolerance was met */
-  double rel_normal_residual; /* ||A^T r_k||_2 / ||A^T r_0||_2 at exit */
-  double normal_residual0;    /* ||A^T r_0||_2 */
+  int32_t iterations;   /* CGLS iterations taken (largest over the plan's problems) */
+  int32_t converged;    /* 1 if the tolerance was met (by every problem) */
+  double rel_normal_residual; /* ||A^T r_k||_2 / ||A^T r_0||_2 at exit (largest) */
+  double normal_residual0;    /* ||A^T r_0||_2 (largest) */
   double rows_kernel_us;      /* timing mode: mean time of one row-kernel launch (q = A p) */
   double cols_kernel_us;      /* timing mode: mean time of one column-kernel launch (A^T r) */
+  int32_t problems;           /* problems solved */
+  int32_t problems_converged; /* problems that met the tolerance */
 } fct_solve_info;
 
 /* ---- errors ------------------------------------------------------------ */
@@ -174,6 +183,28 @@ fct_status fct_plan_export(const fct_plan* plan, int64_t* d_alias, int32_t* d_pe
  * sampler: host_out[k] = cos(pi k / N), k = 0..N (synchronous). */
 fct_status fct_grid_nodes(const fct_plan* plan, int32_t grid, int32_t dim,
                           double* host_out);
+
+/* ---- batches of independent problems ------------------------------------
+ *
+ * fct_batch_create: packs `count` single-problem plans (same device) into
+ * one batch plan whose buffers are the concatenation of the problems'
+ * buffers in order: samples (problem p's grids at point_offset(p)), b (its
+ * rows at row_offset(p)) and c (its coefficients at col_offset(p)).  A
+ * batch plan is accepted by fct_dct, fct_dct_full, fct_apply_A, fct_apply_AT,
+ * fct_solve and by fct_sample with FCT_F_PLANTED (d_coeffs concatenated);
+ * every DCT level and every CGLS half-iteration of all problems is one kernel
+ * launch.  The solve keeps separate CG scalars, convergence tests and
+ * reduction orders per problem, so each problem's result is bitwise the same
+ * as when it is solved alone.  The source plans are only read during the
+ * call and may be destroyed afterwards.  Synchronous.
+ * Limits: sum of K*n_support < 2^31, sum of rows < 2^31.
+ */
+fct_status fct_batch_create(int32_t count, const fct_plan* const* plans,
+                            hipStream_t stream, fct_plan** out);
+/* Layout of problem p of a plan (any pointer may be NULL). */
+fct_status fct_plan_problem(const fct_plan* plan, int32_t p, int64_t* n_support,
+                            int64_t* rows, int64_t* col_offset, int64_t* row_offset,
+                            int64_t* point_offset, int64_t* points);
 
 /* ---- workspaces ---------------------------------------------------------
  * Device scratch for one stream: the DCT intermediate tensor (P_total
@@ -229,6 +260,8 @@ fct_status fct_apply_AT(const fct_plan* plan, const double* d_r, double* d_s,
 fct_status fct_solve(const fct_plan* plan, const double* d_b, double* d_c,
                      const fct_solve_opts* opts, fct_solve_info* info,
                      fct_ws* ws, hipStream_t stream);
+/* Result of problem p in the workspace's last fct_solve (host copy). */
+fct_status fct_ws_problem_info(const fct_ws* ws, int32_t p, fct_solve_info* out);
 
 #ifdef __cplusplus
 }

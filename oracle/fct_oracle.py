@@ -43,7 +43,7 @@ __all__ = [
     "idct_grid", "alias_bins", "build_plan", "Plan", "sample_planted",
     "sample_function", "sample_problem", "rhs_from_transforms",
     "dense_A", "sparse_A", "lstsq_qr", "lstsq_normal", "rank_check",
-    "gram_matrix", "normal_residual", "fct_solve", "max_rel_err",
+    "gram_matrix", "normal_residual", "fct_solve", "max_rel_err", "lstsq_lsqr",
     "mean_l2_err", "fold_injective",
 ]
 
@@ -418,6 +418,15 @@ def lstsq_normal(plan: Plan, b: np.ndarray) -> np.ndarray:
     h = As.T @ b
     cf = sla.cho_factor(Gm, lower=False, overwrite_a=True, check_finite=False)
     return sla.cho_solve(cf, h, check_finite=False)
+
+
+def lstsq_lsqr(plan: Plan, b: np.ndarray, tol: float = 1e-15, iter_lim: int = 20000):
+    """argmin ||b - A c||_2 by LSQR on the explicit sparse A (scipy's
+    Golub-Kahan bidiagonalisation); for supports too large for dense QR.
+    Returns (c, iterations, LSQR's condition estimate)."""
+    import scipy.sparse.linalg as spl
+    res = spl.lsqr(sparse_A(plan), b, atol=tol, btol=tol, conlim=1e12, iter_lim=iter_lim)
+    return res[0], int(res[2]), float(res[6])
 
 
 def rank_check(plan: Plan, kappa_max: float = 1e4):

@@ -1,6 +1,6 @@
 // The stacked operator A and the CGLS least-squares iteration (Sec. 3.4,
 // Alg. 3: c* = argmin_c || F f - A c ||_2, solved by conjugate gradients on
-// the normal equations).
+// the normal equations), for one problem or a batch of independent problems.
 //
 // A is applied without atomics.  q = A c sums, for each row (non-empty bin),
 // the support entries that alias to it; the plan stores those entries
@@ -10,11 +10,18 @@
 // partials are summed in a fixed order by every consumer, so every run gives
 // the same bits.
 //
+// A batch is the block-diagonal system of its problems, but every problem
+// keeps its own CG scalars, convergence test and reduction order: a
+// workgroup only ever covers rows (or columns) of one problem, and the
+// problem's partials are summed over its own workgroups in a fixed order.
+// A problem's arithmetic is therefore identical alone and in any batch.
+//
 // Layout: the row vectors r and q are interleaved as (r, q) pairs and the
 // column vectors p and s as (p, s) pairs, so each gather is one 16-byte load.
 // The row kernel reads a row's first entries from a 4-wide padded copy of
 // perm ("ell"), which saves the dependent load of the row's offset; longer
-// rows continue in perm.
+// rows continue in perm.  Each workgroup finds its problem and range in one
+// uniform (scalar) load of its block descriptor.
 //
 // One CGLS iteration is two kernels.  With k the iteration number:
 //   rows_k: gamma_k = ||s_k||^2 (from the column partials), convergence test,
@@ -25,11 +32,13 @@
 //   cols_k: alpha_k = gamma_k / ||q_k||^2,
 //           p_k = s_k + beta_{k-1} p_{k-1} (stored), c_{k+1} = c_k + alpha_k p_k,
 //           s_{k+1} = A^T (r_k - alpha_k q_k), partials of ||s_{k+1}||^2.
-// Scalars live in per-iteration history arrays written by workgroup 0 and
-// read by the next kernel, so no value is overwritten while another
-// workgroup of the same launch may still read it.  The iteration number is
-// a device-side base plus a launch-time offset, which lets a fixed chunk of
-// iterations be captured once in a HIP graph and replayed.
+// Per problem, gamma and alpha live in rings of four entries indexed by
+// k mod 4, written by the problem's first workgroup and read by the next
+// kernel: a launch reads entries k-1 (and k) and writes entry k, so no
+// workgroup reads a value that another workgroup of the same launch is
+// overwriting.  The iteration number is a device-side base plus a
+// launch-time offset, which lets a fixed chunk of iterations be captured
+// once in a HIP graph and replayed.
 #include "fct_internal.h"
 
 namespace fct {
@@ -54,12 +63,19 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Fixed-order sum of per-workgroup partials (same value in every workgroup).
-__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int64_t np,
-                                               double* sh) {
+// This thread's share of a problem's per-workgroup partials.
+__device__ __forceinline__ double load_partials(const double* __restrict__ part, int32_t off,
+                                                int32_t np) {
   double v = 0.0;
-  for (int64_t i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
-  return block_sum(v, sh);
+  for (int32_t i = threadIdx.x; i < np; i += blockDim.x) v += part[off + i];
+  return v;
+}
+
+__device__ __forceinline__ double ring_gamma(const double* ring, int p, int k) {
+  return ring[p * 8 + (k & 3)];
+}
+__device__ __forceinline__ double ring_alpha(const double* ring, int p, int k) {
+  return ring[p * 8 + 4 + (k & 3)];
 }
 
 __global__ __launch_bounds__(kBlock) void apply_A_kernel(const int32_t* __restrict__ seg_off,
@@ -74,24 +90,29 @@ __global__ __launch_bounds__(kBlock) void apply_A_kernel(const int32_t* __restri
   q[row] = acc;
 }
 
-__global__ __launch_bounds__(kBlock) void apply_AT_kernel(const int32_t* __restrict__ rowmap,
-                                                          int K, int64_t n,
+__global__ __launch_bounds__(kBlock) void apply_AT_kernel(const ColBlock* __restrict__ cblk,
+                                                          const int32_t* __restrict__ rowmap,
                                                           const double* __restrict__ r,
                                                           double* __restrict__ s) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  const ColBlock bd = cblk[blockIdx.x];
+  const int32_t j = bd.col0 + threadIdx.x;          // global column
+  if (j >= bd.col_end) return;
+  const int32_t jl = j - bd.col_off;                 // column within its problem
   double acc = 0.0;
-  for (int l = 0; l < K; ++l) acc += r[rowmap[(int64_t)l * n + j]];
+  for (int l = 0; l < bd.K; ++l) acc += r[rowmap[bd.rmap_off + l * bd.n + jl]];
   s[j] = acc;
 }
 
-// r_0 = b - A c_0 (c_0 = 0 unless warm), q = 0, iteration state reset.
+// r_0 = b - A c_0 (c_0 = 0 unless warm), q = 0; resets the iteration state.
 __global__ __launch_bounds__(kBlock) void cgls_init_rows_kernel(CglsArgs a,
                                                                 const double* __restrict__ b,
                                                                 int warm) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row == 0) { a.state[0] = 0; a.state[1] = 0; a.state[2] = 0; }
-  if (row >= a.M) return;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) a.state[0] = 0;
+  if (g < a.nprob) { a.done[g] = 0; a.flags[g] = 0; }
+  const RowBlock bd = a.rblk[blockIdx.x];
+  const int32_t row = bd.row0 + threadIdx.x;
+  if (row >= bd.row_end) return;
   double acc = 0.0;
   if (warm) {
     const int32_t t1 = a.seg_off[row + 1];
@@ -103,10 +124,12 @@ __global__ __launch_bounds__(kBlock) void cgls_init_rows_kernel(CglsArgs a,
 // s_0 = A^T r_0, p = 0, c = 0 unless warm, partials of ||s_0||^2.
 __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int warm) {
   __shared__ double sh[16];
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const ColBlock bd = a.cblk[blockIdx.x];
+  const int32_t j = bd.col0 + threadIdx.x;
   double sv = 0.0;
-  if (j < a.n) {
-    for (int l = 0; l < a.K; ++l) sv += a.rq[a.rowmap[(int64_t)l * a.n + j]].x;
+  if (j < bd.col_end) {
+    const int32_t jl = j - bd.col_off;
+    for (int l = 0; l < bd.K; ++l) sv += a.rq[a.rowmap[bd.rmap_off + l * bd.n + jl]].x;
     a.ps[j] = make_double2(0.0, sv);
     if (!warm) a.c[j] = 0.0;
   }
@@ -118,24 +141,20 @@ __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int 
 // are known; further grids continue in a loop.
 constexpr int kPrefetch = 4;
 
-// This thread's share of the other kernel's per-workgroup sums (loaded
-// before the state check so the loads overlap).
-__device__ __forceinline__ double load_partials(const double* __restrict__ part, int64_t np) {
-  double v = 0.0;
-  for (int64_t i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
-  return v;
-}
-
-__global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel,
-                                                           int64_t ncolblocks) {
+__global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) {
   __shared__ double sh[16];
-  __shared__ int s_state[2];
-  // one read per workgroup, so every wave of it takes the same branch
-  if (threadIdx.x == 0) { s_state[0] = a.state[0]; s_state[1] = a.state[1]; }
-  const double gpart = load_partials(a.part_s, ncolblocks);
+  __shared__ int s_done;
+  const RowBlock bd = a.rblk[blockIdx.x];            // uniform: one scalar load
+  const int p = bd.prob;
+  // the problem's stop flag is read once per workgroup (thread 0, through
+  // LDS), so all of its waves take the same branch even if the problem's
+  // first workgroup sets the flag during this launch
+  if (threadIdx.x == 0) s_done = a.done[p];
+  const int base = a.state[0];
+  const double gpart = load_partials(a.part_s, bd.cblk_off, bd.ncblk);
   // operands that do not depend on this iteration's scalars
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = row < a.M;
+  const int32_t row = bd.row0 + threadIdx.x;
+  const bool active = row < bd.row_end;
   double2 rq_old = make_double2(0.0, 0.0);
   int4 e = make_int4(-1, -1, -1, -1);
   if (active) {
@@ -148,10 +167,14 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel,
   const double2 v2 = e.z >= 0 ? a.ps[e.z] : z;
   const double2 v3 = e.w >= 0 ? a.ps[e.w] : z;
   __syncthreads();
-  if (s_state[0] != 0) return;                       // converged or stopped earlier
-  const int k = s_state[1] + rel;
+  if (s_done != 0) return;                           // problem converged or stopped
+  const int k = base + rel;
   double gprev = 1.0, g0 = 0.0, alpha_prev = 0.0;
-  if (k > 0) { gprev = a.hist_gamma[k - 1]; g0 = a.hist_gamma[0]; alpha_prev = a.hist_alpha[k - 1]; }
+  if (k > 0) {
+    gprev = ring_gamma(a.ring, p, k - 1);
+    alpha_prev = ring_alpha(a.ring, p, k - 1);
+    g0 = a.gamma0[p];
+  }
   const double gamma = block_sum(gpart, sh);
   double beta = 0.0;
   bool stop;
@@ -161,9 +184,10 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel,
     beta = gamma / gprev;
     stop = !(gamma > a.tol2 * g0);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.hist_gamma[k] = gamma;
-    if (stop) a.state[0] = k + 1;
+  if (bd.first && threadIdx.x == 0) {
+    a.ring[p * 8 + (k & 3)] = gamma;
+    if (k == 0) a.gamma0[p] = gamma;
+    if (stop) a.done[p] = k + 1;
   }
   if (stop) return;
   double qv = 0.0;
@@ -186,14 +210,17 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel,
   if (threadIdx.x == 0) a.part_q[blockIdx.x] = part;
 }
 
-__global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel,
-                                                           int64_t nrowblocks) {
+__global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) {
   __shared__ double sh[16];
-  __shared__ int s_state[2];
-  if (threadIdx.x == 0) { s_state[0] = a.state[0]; s_state[1] = a.state[1]; }
-  const double dpart = load_partials(a.part_q, nrowblocks);
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = j < a.n;
+  __shared__ int s_done;
+  const ColBlock bd = a.cblk[blockIdx.x];
+  const int p = bd.prob;
+  if (threadIdx.x == 0) s_done = a.done[p];
+  const int base = a.state[0];
+  const double dpart = load_partials(a.part_q, bd.rblk_off, bd.nrblk);
+  const int32_t j = bd.col0 + threadIdx.x;
+  const bool active = j < bd.col_end;
+  const int32_t jl = j - bd.col_off;
   double2 ps_old = make_double2(0.0, 0.0);
   double c_old = 0.0;
   double2 g[kPrefetch];
@@ -204,30 +231,30 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel,
 #pragma unroll
   for (int l = 0; l < kPrefetch; ++l) {
     g[l] = make_double2(0.0, 0.0);
-    if (active && l < a.K) g[l] = a.rq[a.rowmap[(int64_t)l * a.n + j]];
+    if (active && l < bd.K) g[l] = a.rq[a.rowmap[bd.rmap_off + l * bd.n + jl]];
   }
   __syncthreads();
-  if (s_state[0] != 0) return;
-  const int k = s_state[1] + rel;
-  const double gamma = a.hist_gamma[k];
-  const double gprev = (k > 0) ? a.hist_gamma[k - 1] : 1.0;
+  if (s_done != 0) return;
+  const int k = base + rel;
+  const double gamma = ring_gamma(a.ring, p, k);
+  const double gprev = (k > 0) ? ring_gamma(a.ring, p, k - 1) : 1.0;
   const double delta = block_sum(dpart, sh);
   const double beta = (k > 0) ? gamma / gprev : 0.0;
   if (!(delta > 0.0)) {                              // A p = 0: breakdown
-    if (blockIdx.x == 0 && threadIdx.x == 0) { a.state[2] = 1; a.state[0] = k + 1; }
+    if (bd.first && threadIdx.x == 0) { a.flags[p] = 1; a.done[p] = k + 1; }
     return;
   }
   const double alpha = gamma / delta;
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.hist_alpha[k] = alpha;
+  if (bd.first && threadIdx.x == 0) a.ring[p * 8 + 4 + (k & 3)] = alpha;
   double sv = 0.0;
   if (active) {
     const double pv = fma(beta, ps_old.x, ps_old.y);
     a.c[j] = fma(alpha, pv, c_old);
 #pragma unroll
     for (int l = 0; l < kPrefetch; ++l)
-      if (l < a.K) sv += fma(-alpha, g[l].y, g[l].x);
-    for (int l = kPrefetch; l < a.K; ++l) {
-      const double2 v = a.rq[a.rowmap[(int64_t)l * a.n + j]];
+      if (l < bd.K) sv += fma(-alpha, g[l].y, g[l].x);
+    for (int l = kPrefetch; l < bd.K; ++l) {
+      const double2 v = a.rq[a.rowmap[bd.rmap_off + l * bd.n + jl]];
       sv += fma(-alpha, v.y, v.x);
     }
     a.ps[j] = make_double2(pv, sv);
@@ -236,25 +263,30 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel,
   if (threadIdx.x == 0) a.part_s[blockIdx.x] = part;
 }
 
-__global__ __launch_bounds__(kBlock) void cgls_gamma_kernel(CglsArgs a, int k,
-                                                            int64_t ncolblocks) {
+// gamma of the current column partials into ring entry k, for every problem
+// that did not stop (one workgroup per problem).
+__global__ __launch_bounds__(kBlock) void cgls_gamma_kernel(CglsArgs a, int k) {
   __shared__ double sh[16];
-  const double gamma = sum_partials(a.part_s, ncolblocks, sh);
-  if (threadIdx.x == 0) a.hist_gamma[k] = gamma;
+  const int p = blockIdx.x;
+  const ProbInfo pi = a.prob[p];
+  const double gamma = block_sum(load_partials(a.part_s, pi.cblk_off, pi.ncblk), sh);
+  if (threadIdx.x == 0 && a.done[p] == 0) a.ring[p * 8 + (k & 3)] = gamma;
 }
 
-__global__ void cgls_set_state_kernel(int32_t* state, int s0, int s1, int s2) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) { state[0] = s0; state[1] = s1; state[2] = s2; }
+__global__ void cgls_set_base_kernel(int32_t* state, int base) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) state[0] = base;
+}
+
+__global__ void cgls_fill_i32_kernel(int32_t* v, int n, int value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = value;
 }
 
 __global__ void cgls_advance_kernel(int32_t* state, int chunk) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) state[1] += chunk;
+  if (threadIdx.x == 0 && blockIdx.x == 0) state[0] += chunk;
 }
 
 }  // namespace
-
-int64_t cgls_row_blocks(int64_t M) { return ceil_div(M, kBlock); }
-int64_t cgls_col_blocks(int64_t n) { return ceil_div(n, kBlock); }
 
 hipError_t launch_apply_A(const int32_t* seg_off, const int32_t* perm, int64_t M, const double* c,
                           double* q, hipStream_t s) {
@@ -263,32 +295,33 @@ hipError_t launch_apply_A(const int32_t* seg_off, const int32_t* perm, int64_t M
   return hipGetLastError();
 }
 
-hipError_t launch_apply_AT(const int32_t* rowmap, int K, int64_t n, const double* r, double* out,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(apply_AT_kernel, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s,
-                     rowmap, K, n, r, out);
+hipError_t launch_apply_AT(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
+                           const double* r, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(apply_AT_kernel, dim3((unsigned)ncblk), dim3(kBlock), 0, s, cblk, rowmap, r,
+                     out);
   return hipGetLastError();
 }
 
 hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_init_rows_kernel, dim3((unsigned)cgls_row_blocks(a.M)), dim3(kBlock), 0,
-                     s, a, b, warm ? 1 : 0);
+  // the row launch also clears the per-problem flags: every problem owns at
+  // least one row block, so there are at least nprob >= ceil(nprob/kBlock)
+  // workgroups
+  hipLaunchKernelGGL(cgls_init_rows_kernel, dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, b,
+                     warm ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cgls_init_cols_kernel, dim3((unsigned)cgls_col_blocks(a.n)), dim3(kBlock), 0,
-                     s, a, warm ? 1 : 0);
+  hipLaunchKernelGGL(cgls_init_cols_kernel, dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a,
+                     warm ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_rows_kernel, dim3((unsigned)cgls_row_blocks(a.M)), dim3(kBlock), 0, s,
-                     a, rel, cgls_col_blocks(a.n));
+  hipLaunchKernelGGL(cgls_rows_kernel, dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, rel);
   return hipGetLastError();
 }
 
 hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_cols_kernel, dim3((unsigned)cgls_col_blocks(a.n)), dim3(kBlock), 0, s,
-                     a, rel, cgls_row_blocks(a.M));
+  hipLaunchKernelGGL(cgls_cols_kernel, dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, rel);
   return hipGetLastError();
 }
 
@@ -299,18 +332,19 @@ hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s) {
 }
 
 hipError_t launch_cgls_gamma(const CglsArgs& a, int k, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_gamma_kernel, dim3(1), dim3(kBlock), 0, s, a, k, cgls_col_blocks(a.n));
+  hipLaunchKernelGGL(cgls_gamma_kernel, dim3((unsigned)a.nprob), dim3(kBlock), 0, s, a, k);
   return hipGetLastError();
 }
 
-hipError_t launch_cgls_timing_state(int32_t* state, int k, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_set_state_kernel, dim3(1), dim3(64), 0, s, state, 0, k, 0);
+hipError_t launch_cgls_set_base(int32_t* state, int base, hipStream_t s) {
+  hipLaunchKernelGGL(cgls_set_base_kernel, dim3(1), dim3(64), 0, s, state, base);
   return hipGetLastError();
 }
 
-hipError_t launch_cgls_timing_state_restore(int32_t* state, int stop, int breakdown,
-                                            hipStream_t s) {
-  hipLaunchKernelGGL(cgls_set_state_kernel, dim3(1), dim3(64), 0, s, state, stop, 0, breakdown);
+hipError_t launch_fill_i32(int32_t* v, int n, int value, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cgls_fill_i32_kernel, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s,
+                     v, n, value);
   return hipGetLastError();
 }
 

@@ -168,7 +168,7 @@ void destroy_plan(fct_plan* p) {
   dfree(p->d_support); dfree(p->d_grids); dfree(p->d_strides); dfree(p->d_point_off);
   dfree(p->d_alias); dfree(p->d_perm); dfree(p->d_seg_off); dfree(p->d_bin_id);
   dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_ell); dfree(p->d_nodes); dfree(p->d_cmat);
-  dfree(p->d_emat);
+  dfree(p->d_emat); dfree(p->d_rblk); dfree(p->d_cblk); dfree(p->d_prob);
   free_levels(p->fwd);
   free_levels(p->fwd_full);
   free_levels(p->inv);
@@ -176,16 +176,17 @@ void destroy_plan(fct_plan* p) {
 }
 
 fct_status build_dct_levels(fct_plan* p) {
-  const int K = p->K, D = p->D;
+  const int K = p->K;
   std::vector<std::vector<Group>> groups(K);
   int maxlev = 0;
   for (int l = 0; l < K; ++l) {
-    groups[l] = make_groups(&p->grids[(size_t)l * D], D);
+    groups[l] = make_groups(&p->grids[(size_t)p->grid_goff[l]], p->grid_D[l]);
     maxlev = std::max(maxlev, (int)groups[l].size());
   }
   std::vector<std::vector<PassDesc>> fwd(maxlev), full(maxlev), inv(maxlev);
   for (int l = 0; l < K; ++l) {
-    const int32_t* g = &p->grids[(size_t)l * D];
+    const int32_t* g = &p->grids[(size_t)p->grid_goff[l]];
+    const int D = p->grid_D[l];
     const auto& gs = groups[l];
     const int np = (int)gs.size();
     const int shift = maxlev - np;   // forward levels aligned at the end
@@ -209,6 +210,72 @@ fct_status build_dct_levels(fct_plan* p) {
   st = upload_levels(full, p->fwd_full, &p->device_bytes);
   if (st != FCT_OK) return st;
   return upload_levels(inv, p->inv, &p->device_bytes);
+}
+
+// Row and column blocks of every problem, and the problem table.  Problem
+// p's rows (columns) are cut into blocks of kBlock starting at its own first
+// row (column), so the blocking -- and with it every reduction order -- of a
+// problem does not depend on the other problems of a batch.
+fct_status build_blocks(fct_plan* p) {
+  std::vector<RowBlock> rb;
+  std::vector<ColBlock> cb;
+  for (int32_t q = 0; q < p->nprob; ++q) {
+    ProbInfo& pi = p->probs[(size_t)q];
+    pi.rblk_off = (int32_t)rb.size();
+    pi.nrblk = (int32_t)ceil_div(pi.M, kBlock);
+    pi.cblk_off = (int32_t)cb.size();
+    pi.ncblk = (int32_t)ceil_div(pi.n, kBlock);
+    for (int32_t b = 0; b < pi.nrblk; ++b) {
+      RowBlock r;
+      std::memset(&r, 0, sizeof(r));
+      r.prob = q;
+      r.row0 = pi.row_off + b * kBlock;
+      r.row_end = std::min(pi.row_off + pi.M, r.row0 + kBlock);
+      r.cblk_off = pi.cblk_off;
+      r.ncblk = pi.ncblk;
+      r.first = b == 0;
+      rb.push_back(r);
+    }
+    for (int32_t b = 0; b < pi.ncblk; ++b) {
+      ColBlock c;
+      std::memset(&c, 0, sizeof(c));
+      c.prob = q;
+      c.col0 = pi.col_off + b * kBlock;
+      c.col_end = std::min(pi.col_off + pi.n, c.col0 + kBlock);
+      c.col_off = pi.col_off;
+      c.rblk_off = pi.rblk_off;
+      c.nrblk = pi.nrblk;
+      c.K = pi.K;
+      c.n = pi.n;
+      c.rmap_off = pi.rmap_off;
+      c.first = b == 0;
+      cb.push_back(c);
+    }
+  }
+  p->nrblk = (int64_t)rb.size();
+  p->ncblk = (int64_t)cb.size();
+  if (p->nrblk > 0x7fffffffLL || p->ncblk > 0x7fffffffLL) {
+    set_error("too many CGLS blocks");
+    return FCT_EINVAL;
+  }
+  int64_t* bytes = &p->device_bytes;
+  FCT_HIP(dalloc(&p->d_rblk, p->nrblk, bytes));
+  FCT_HIP(dalloc(&p->d_cblk, p->ncblk, bytes));
+  FCT_HIP(dalloc(&p->d_prob, (int64_t)p->nprob, bytes));
+  FCT_HIP(hipMemcpy(p->d_rblk, rb.data(), sizeof(RowBlock) * rb.size(), hipMemcpyHostToDevice));
+  FCT_HIP(hipMemcpy(p->d_cblk, cb.data(), sizeof(ColBlock) * cb.size(), hipMemcpyHostToDevice));
+  FCT_HIP(hipMemcpy(p->d_prob, p->probs.data(), sizeof(ProbInfo) * p->probs.size(),
+                    hipMemcpyHostToDevice));
+  return FCT_OK;
+}
+
+fct_status build_tables(fct_plan* p, hipStream_t stream) {
+  int64_t* bytes = &p->device_bytes;
+  FCT_HIP(dalloc(&p->d_nodes, (int64_t)(p->maxdeg + 1) * 64, bytes));
+  FCT_HIP(dalloc(&p->d_cmat, mat_offset(p->maxdeg + 1), bytes));
+  FCT_HIP(dalloc(&p->d_emat, mat_offset(p->maxdeg + 1), bytes));
+  FCT_HIP(launch_tables(p->maxdeg, p->d_nodes, p->d_cmat, p->d_emat, stream));
+  return FCT_OK;
 }
 
 fct_status validate_inputs(int32_t D, int64_t n, const int32_t* S, int32_t K, const int32_t* G,
@@ -277,6 +344,11 @@ bool dev_ok(const fct_plan* p) {
   return true;
 }
 
+struct DevGuard {
+  std::vector<void*> ptrs;
+  ~DevGuard() { for (void* q : ptrs) if (q) (void)hipFree(q); }
+};
+
 }  // namespace
 
 }  // namespace fct
@@ -324,8 +396,12 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   } guard{p};
 
   FCT_HIP(hipGetDevice(&p->device));
+  p->nprob = 1;
   p->D = D; p->K = K; p->n = n;
   p->grids.assign(grids, grids + (size_t)K * D);
+  p->grid_D.assign((size_t)K, D);
+  p->grid_goff.resize((size_t)K + 1);
+  for (int l = 0; l <= K; ++l) p->grid_goff[(size_t)l] = (int64_t)l * D;
   p->points.resize(K);
   p->point_off.assign((size_t)K + 1, 0);
   std::vector<int64_t> strides((size_t)K * D);
@@ -355,9 +431,6 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   FCT_HIP(dalloc(&p->d_bin_id, L, bytes));
   FCT_HIP(dalloc(&p->d_rowmap, L, bytes));
   FCT_HIP(dalloc(&p->d_row_off, (int64_t)K + 1, bytes));
-  FCT_HIP(dalloc(&p->d_nodes, (int64_t)(p->maxdeg + 1) * 64, bytes));
-  FCT_HIP(dalloc(&p->d_cmat, mat_offset(p->maxdeg + 1), bytes));
-  FCT_HIP(dalloc(&p->d_emat, mat_offset(p->maxdeg + 1), bytes));
   FCT_HIP(dalloc(&guard.k0, L, nullptr));
   FCT_HIP(dalloc(&guard.k1, L, nullptr));
   FCT_HIP(dalloc(&guard.v0, L, nullptr));
@@ -370,7 +443,8 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   FCT_HIP(hipMemcpyAsync(p->d_strides, strides.data(), sizeof(int64_t) * K * D, hipMemcpyHostToDevice, stream));
   FCT_HIP(hipMemcpyAsync(p->d_point_off, p->point_off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, stream));
 
-  FCT_HIP(launch_tables(p->maxdeg, p->d_nodes, p->d_cmat, p->d_emat, stream));
+  st = build_tables(p, stream);
+  if (st != FCT_OK) return st;
   FCT_HIP(launch_alias(p->d_support, p->d_grids, p->d_strides, D, n, K, p->d_alias, guard.k0,
                        guard.v0, stream));
   bool in_tmp = false;
@@ -388,6 +462,111 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   FCT_HIP(launch_ell(p->d_seg_off, p->d_perm, p->M, p->d_ell, stream));
   FCT_HIP(hipStreamSynchronize(stream));
 
+  ProbInfo pi;
+  std::memset(&pi, 0, sizeof(pi));
+  pi.row_off = 0; pi.M = (int32_t)p->M; pi.col_off = 0; pi.n = (int32_t)n;
+  pi.K = K; pi.rmap_off = 0; pi.grid_off = 0;
+  p->probs.assign(1, pi);
+  p->prob_point_off = {0, p->total_points};
+  st = build_blocks(p);
+  if (st != FCT_OK) return st;
+  st = build_dct_levels(p);
+  if (st != FCT_OK) return st;
+  guard.p = nullptr;
+  *out = p;
+  return FCT_OK;
+}
+
+fct_status fct_batch_create(int32_t count, const fct_plan* const* plans, hipStream_t stream,
+                            fct_plan** out) {
+  g_last_error.clear();
+  if (!out || !plans || count < 1) { set_error("need count >= 1 plans and an output"); return FCT_EINVAL; }
+  *out = nullptr;
+  int dev = -1;
+  FCT_HIP(hipGetDevice(&dev));
+  int64_t Lsum = 0, Msum = 0, nsum = 0, Ksum = 0;
+  for (int32_t q = 0; q < count; ++q) {
+    const fct_plan* s = plans[q];
+    if (!s || s->nprob != 1) { set_error("plan %d is NULL or already a batch", q); return FCT_EINVAL; }
+    if (s->device != dev) { set_error("plan %d lives on another device", q); return FCT_EINVAL; }
+    Lsum += (int64_t)s->K * s->n;
+    Msum += s->M;
+    nsum += s->n;
+    Ksum += s->K;
+  }
+  if (Lsum >= 0x7fffffffLL || Msum >= 0x7fffffffLL || Ksum >= (1 << 24)) {
+    set_error("batch too large (sum K*n = %lld, rows = %lld)", (long long)Lsum, (long long)Msum);
+    return FCT_EINVAL;
+  }
+  fct_plan* p = new (std::nothrow) fct_plan();
+  if (!p) { set_error("host allocation failed"); return FCT_ENOMEM; }
+  struct Guard { fct_plan* p; ~Guard() { if (p) destroy_plan(p); } } guard{p};
+  p->device = dev;
+  p->nprob = count;
+  p->K = (int32_t)Ksum;
+  p->n = nsum;
+  p->M = Msum;
+  int64_t* bytes = &p->device_bytes;
+  FCT_HIP(dalloc(&p->d_perm, Lsum, bytes));
+  FCT_HIP(dalloc(&p->d_seg_off, Msum + 1, bytes));
+  FCT_HIP(dalloc(&p->d_bin_id, Msum, bytes));
+  FCT_HIP(dalloc(&p->d_rowmap, Lsum, bytes));
+  FCT_HIP(dalloc(&p->d_ell, Msum, bytes));
+
+  p->grid_goff.push_back(0);
+  p->point_off.push_back(0);
+  p->row_off.push_back(0);
+  p->prob_point_off.push_back(0);
+  int64_t loff = 0, moff = 0, noff = 0;
+  for (int32_t q = 0; q < count; ++q) {
+    const fct_plan* s = plans[q];
+    const int64_t Lq = (int64_t)s->K * s->n;
+    ProbInfo pi;
+    std::memset(&pi, 0, sizeof(pi));
+    pi.row_off = (int32_t)moff; pi.M = (int32_t)s->M;
+    pi.col_off = (int32_t)noff; pi.n = (int32_t)s->n;
+    pi.K = s->K; pi.rmap_off = (int32_t)loff;
+    pi.grid_off = (int32_t)p->points.size();
+    p->probs.push_back(pi);
+    FCT_HIP(launch_copy_add_i32(p->d_perm + loff, s->d_perm, Lq, (int32_t)noff, stream));
+    FCT_HIP(launch_copy_add_i32(p->d_seg_off + moff, s->d_seg_off, s->M, (int32_t)loff, stream));
+    FCT_HIP(launch_copy_add_i32(p->d_rowmap + loff, s->d_rowmap, Lq, (int32_t)moff, stream));
+    FCT_HIP(launch_copy_ell(p->d_ell + moff, s->d_ell, s->M, (int32_t)noff, (int32_t)loff, stream));
+    FCT_HIP(hipMemcpyAsync(p->d_bin_id + moff, s->d_bin_id, sizeof(int64_t) * s->M,
+                           hipMemcpyDeviceToDevice, stream));
+    for (int32_t l = 0; l < s->K; ++l) {
+      const int32_t D = s->grid_D[(size_t)l];
+      const int32_t* g = &s->grids[(size_t)s->grid_goff[(size_t)l]];
+      p->grids.insert(p->grids.end(), g, g + D);
+      p->grid_D.push_back(D);
+      p->grid_goff.push_back((int64_t)p->grids.size());
+      p->points.push_back(s->points[(size_t)l]);
+      p->point_off.push_back(p->point_off.back() + s->points[(size_t)l]);
+      p->row_off.push_back((int32_t)(moff + s->row_off[(size_t)l + 1]));
+      p->max_points = std::max(p->max_points, s->points[(size_t)l]);
+    }
+    p->prob_point_off.push_back(p->point_off.back());
+    p->D = std::max(p->D, s->D);
+    p->maxdeg = std::max(p->maxdeg, s->maxdeg);
+    loff += Lq; moff += s->M; noff += s->n;
+  }
+  p->total_points = p->point_off.back();
+  const int32_t end = (int32_t)Lsum;
+  FCT_HIP(hipMemcpyAsync(p->d_seg_off + Msum, &end, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  FCT_HIP(dalloc(&p->d_grids, (int64_t)p->grids.size(), bytes));
+  FCT_HIP(dalloc(&p->d_point_off, (int64_t)p->K + 1, bytes));
+  FCT_HIP(dalloc(&p->d_row_off, (int64_t)p->K + 1, bytes));
+  FCT_HIP(hipMemcpyAsync(p->d_grids, p->grids.data(), sizeof(int32_t) * p->grids.size(),
+                         hipMemcpyHostToDevice, stream));
+  FCT_HIP(hipMemcpyAsync(p->d_point_off, p->point_off.data(), sizeof(int64_t) * (p->K + 1),
+                         hipMemcpyHostToDevice, stream));
+  FCT_HIP(hipMemcpyAsync(p->d_row_off, p->row_off.data(), sizeof(int32_t) * (p->K + 1),
+                         hipMemcpyHostToDevice, stream));
+  fct_status st = build_tables(p, stream);
+  if (st != FCT_OK) return st;
+  FCT_HIP(hipStreamSynchronize(stream));
+  st = build_blocks(p);
+  if (st != FCT_OK) return st;
   st = build_dct_levels(p);
   if (st != FCT_OK) return st;
   guard.p = nullptr;
@@ -399,9 +578,11 @@ void fct_plan_destroy(fct_plan* plan) { destroy_plan(plan); }
 
 fct_status fct_plan_get_info(const fct_plan* p, fct_plan_info* o) {
   if (!p || !o) { set_error("NULL argument"); return FCT_EINVAL; }
+  std::memset(o, 0, sizeof(*o));
   o->D = p->D; o->K = p->K; o->n_support = p->n; o->total_points = p->total_points;
   o->total_rows = p->M; o->max_points = p->max_points; o->max_degree = p->maxdeg;
   o->dct_levels = (int32_t)p->fwd.size(); o->device_bytes = p->device_bytes;
+  o->problems = p->nprob;
   return FCT_OK;
 }
 
@@ -415,12 +596,28 @@ fct_status fct_plan_grid(const fct_plan* p, int32_t l, int64_t* points, int64_t*
   return FCT_OK;
 }
 
+fct_status fct_plan_problem(const fct_plan* p, int32_t q, int64_t* n, int64_t* rows,
+                            int64_t* col_offset, int64_t* row_offset, int64_t* point_offset,
+                            int64_t* points) {
+  if (!p || q < 0 || q >= p->nprob) { set_error("bad plan or problem index"); return FCT_EINVAL; }
+  const ProbInfo& pi = p->probs[(size_t)q];
+  if (n) *n = pi.n;
+  if (rows) *rows = pi.M;
+  if (col_offset) *col_offset = pi.col_off;
+  if (row_offset) *row_offset = pi.row_off;
+  if (point_offset) *point_offset = p->prob_point_off[(size_t)q];
+  if (points) *points = p->prob_point_off[(size_t)q + 1] - p->prob_point_off[(size_t)q];
+  return FCT_OK;
+}
+
 fct_status fct_plan_export(const fct_plan* p, int64_t* d_alias, int32_t* d_perm,
                            int32_t* d_seg_off, int64_t* d_bin_id, int32_t* d_rowmap,
                            hipStream_t s) {
   if (!p) { set_error("NULL plan"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
-  const int64_t L = (int64_t)p->K * p->n;
+  int64_t L = 0;
+  for (const auto& pi : p->probs) L += (int64_t)pi.K * pi.n;
+  if (d_alias && !p->d_alias) { set_error("alias bins are kept for single-problem plans only"); return FCT_EINVAL; }
   if (d_alias) FCT_HIP(hipMemcpyAsync(d_alias, p->d_alias, sizeof(int64_t) * L, hipMemcpyDeviceToDevice, s));
   if (d_perm) FCT_HIP(hipMemcpyAsync(d_perm, p->d_perm, sizeof(int32_t) * L, hipMemcpyDeviceToDevice, s));
   if (d_seg_off) FCT_HIP(hipMemcpyAsync(d_seg_off, p->d_seg_off, sizeof(int32_t) * (p->M + 1), hipMemcpyDeviceToDevice, s));
@@ -430,12 +627,12 @@ fct_status fct_plan_export(const fct_plan* p, int64_t* d_alias, int32_t* d_perm,
 }
 
 fct_status fct_grid_nodes(const fct_plan* p, int32_t grid, int32_t dim, double* host_out) {
-  if (!p || !host_out || grid < 0 || grid >= p->K || dim < 0 || dim >= p->D) {
+  if (!p || !host_out || grid < 0 || grid >= p->K || dim < 0 || dim >= p->grid_D[(size_t)grid]) {
     set_error("bad arguments");
     return FCT_EINVAL;
   }
   if (!dev_ok(p)) return FCT_EINVAL;
-  const int N = p->grids[(size_t)grid * p->D + dim];
+  const int N = p->grids[(size_t)p->grid_goff[(size_t)grid] + dim];
   FCT_HIP(hipMemcpy(host_out, p->d_nodes + (int64_t)N * 64, sizeof(double) * (N + 1),
                     hipMemcpyDeviceToHost));
   return FCT_OK;
@@ -450,17 +647,24 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   struct G { fct_ws* w; ~G() { if (w) fct_ws_destroy(w); } } guard{w};
   w->device = p->device;
   w->plan = p;
+  const int64_t P = p->nprob;
   FCT_HIP(dalloc(&w->d_scratch, p->total_points, nullptr));
   FCT_HIP(dalloc(&w->d_rq, p->M, nullptr));
   FCT_HIP(dalloc(&w->d_ps, p->n, nullptr));
   FCT_HIP(dalloc(&w->d_ctmp, p->n, nullptr));
-  FCT_HIP(dalloc(&w->d_part_q, cgls_row_blocks(p->M), nullptr));
-  FCT_HIP(dalloc(&w->d_part_s, cgls_col_blocks(p->n), nullptr));
-  FCT_HIP(dalloc(&w->d_hist_gamma, kMaxHistory, nullptr));
-  FCT_HIP(dalloc(&w->d_hist_alpha, kMaxHistory, nullptr));
+  FCT_HIP(dalloc(&w->d_part_q, p->nrblk, nullptr));
+  FCT_HIP(dalloc(&w->d_part_s, p->ncblk, nullptr));
+  FCT_HIP(dalloc(&w->d_ring, 8 * P, nullptr));
+  FCT_HIP(dalloc(&w->d_gamma0, P, nullptr));
+  FCT_HIP(dalloc(&w->d_done, P, nullptr));
+  FCT_HIP(dalloc(&w->d_flags, P, nullptr));
+  FCT_HIP(dalloc(&w->d_done_tmp, P, nullptr));
   FCT_HIP(dalloc(&w->d_state, 4, nullptr));
-  FCT_HIP(hipHostMalloc((void**)&w->h_state, sizeof(int32_t) * 8, hipHostMallocDefault));
-  FCT_HIP(hipHostMalloc((void**)&w->h_gamma, sizeof(double) * 6, hipHostMallocDefault));
+  FCT_HIP(dalloc(&w->d_state_tmp, 4, nullptr));
+  FCT_HIP(hipHostMalloc((void**)&w->h_done, sizeof(int32_t) * 3 * P, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_ring, sizeof(double) * 3 * 8 * P, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_gamma0, sizeof(double) * 3 * P, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_flags, sizeof(int32_t) * P, hipHostMallocDefault));
   for (auto& e : w->ev) FCT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   FCT_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
   guard.w = nullptr;
@@ -474,10 +678,13 @@ void fct_ws_destroy(fct_ws* w) {
   if (w->graph_stream) (void)hipStreamDestroy(w->graph_stream);
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
   dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
-  dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_hist_gamma); dfree(w->d_hist_alpha);
-  dfree(w->d_state);
-  if (w->h_state) (void)hipHostFree(w->h_state);
-  if (w->h_gamma) (void)hipHostFree(w->h_gamma);
+  dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_ring); dfree(w->d_gamma0);
+  dfree(w->d_done); dfree(w->d_flags); dfree(w->d_done_tmp); dfree(w->d_state);
+  dfree(w->d_state_tmp);
+  if (w->h_done) (void)hipHostFree(w->h_done);
+  if (w->h_ring) (void)hipHostFree(w->h_ring);
+  if (w->h_gamma0) (void)hipHostFree(w->h_gamma0);
+  if (w->h_flags) (void)hipHostFree(w->h_flags);
   delete w;
 }
 
@@ -491,7 +698,6 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
                       const double* d_coeffs, double* d_samples, fct_ws* ws, hipStream_t s) {
   if (!p || !d_samples) { set_error("NULL plan or output"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
-  const int D = p->D;
   if (family == FCT_F_PLANTED) {
     if (!d_coeffs) { set_error("planted family needs d_coeffs"); return FCT_EINVAL; }
     fct_status st = check_ws(p, ws);
@@ -500,9 +706,14 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
     double* q = reinterpret_cast<double*>(ws->d_rq);   // M doubles of scratch
     FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_coeffs, q, s));
     for (const auto& lv : p->inv)
-      FCT_HIP(launch_dct_level(lv, q, nullptr, d_samples, p->d_emat, p->d_bin_id, s));
+      FCT_HIP(launch_dct_level(lv, FCT_DCT_F64, q, nullptr, d_samples, p->d_emat, p->d_bin_id, s));
     return FCT_OK;
   }
+  if (p->nprob != 1) {
+    set_error("analytic families are sampled per problem (use each problem's own plan)");
+    return FCT_EINVAL;
+  }
+  const int D = p->D;
   int need = 0;
   switch (family) {
     case FCT_F_EXPCOS: need = 2 * D; break;
@@ -519,22 +730,19 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
   std::memset(&prm, 0, sizeof(prm));
   for (int i = 0; i < need; ++i) prm.v[i] = params[i];
   FCT_HIP(launch_sample(family, prm, D, p->K, p->d_grids, p->d_point_off, p->total_points,
-                               p->d_nodes, d_samples, s));
+                        p->d_nodes, d_samples, s));
   return FCT_OK;
 }
 
-static fct_status run_levels(const fct_plan* p, const std::vector<DctLevel>& levels,
-                             const double* in, double* out, int32_t mode, fct_ws* ws,
-                             hipStream_t s) {
-  if (mode != FCT_DCT_F64) { set_error("unsupported DCT mode %d", mode); return FCT_EINVAL; }
-  double* scratch = nullptr;
-  if (levels.size() > 1) {
-    fct_status st = check_ws(p, ws);
-    if (st != FCT_OK) return st;
-    scratch = ws->d_scratch;
+static fct_status check_mode(const fct_plan* p, int32_t mode) {
+  if (mode != FCT_DCT_F64 && mode != FCT_DCT_F32 && mode != FCT_DCT_BF16X3) {
+    set_error("unknown DCT mode %d", mode);
+    return FCT_EINVAL;
   }
-  for (const auto& lv : levels)
-    FCT_HIP(launch_dct_level(lv, in, scratch, out, p->d_cmat, p->d_bin_id, s));
+  if (mode != FCT_DCT_F64 && p->maxdeg > 31) {
+    set_error("DCT mode %d needs every degree <= 31 (plan has %d)", mode, p->maxdeg);
+    return FCT_EINVAL;
+  }
   return FCT_OK;
 }
 
@@ -542,16 +750,28 @@ fct_status fct_dct(const fct_plan* p, const double* d_samples, double* d_b, int3
                    fct_ws* ws, hipStream_t s) {
   if (!p || !d_samples || !d_b) { set_error("NULL argument"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
-  return run_levels(p, p->fwd, d_samples, d_b, mode, ws, s);
+  fct_status st = check_mode(p, mode);
+  if (st != FCT_OK) return st;
+  void* scratch = nullptr;
+  if (p->fwd.size() > 1) {
+    st = check_ws(p, ws);
+    if (st != FCT_OK) return st;
+    scratch = ws->d_scratch;
+  }
+  for (const auto& lv : p->fwd)
+    FCT_HIP(launch_dct_level(lv, mode, d_samples, scratch, d_b, p->d_cmat, p->d_bin_id, s));
+  return FCT_OK;
 }
 
 fct_status fct_dct_full(const fct_plan* p, const double* d_samples, double* d_out, int32_t mode,
                         fct_ws* ws, hipStream_t s) {
+  (void)ws;
   if (!p || !d_samples || !d_out) { set_error("NULL argument"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
-  if (mode != FCT_DCT_F64) { set_error("unsupported DCT mode %d", mode); return FCT_EINVAL; }
+  fct_status st = check_mode(p, mode);
+  if (st != FCT_OK) return st;
   for (const auto& lv : p->fwd_full)
-    FCT_HIP(launch_dct_level(lv, d_samples, nullptr, d_out, p->d_cmat, p->d_bin_id, s));
+    FCT_HIP(launch_dct_level(lv, mode, d_samples, nullptr, d_out, p->d_cmat, p->d_bin_id, s));
   return FCT_OK;
 }
 
@@ -565,7 +785,7 @@ fct_status fct_apply_A(const fct_plan* p, const double* d_c, double* d_q, hipStr
 fct_status fct_apply_AT(const fct_plan* p, const double* d_r, double* d_s, hipStream_t s) {
   if (!p || !d_r || !d_s) { set_error("NULL argument"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
-  FCT_HIP(launch_apply_AT(p->d_rowmap, p->K, p->n, d_r, d_s, s));
+  FCT_HIP(launch_apply_AT(p->d_cblk, p->ncblk, p->d_rowmap, d_r, d_s, s));
   return FCT_OK;
 }
 
@@ -584,16 +804,15 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   if (o.check_every <= 0) o.check_every = 32;
   if (o.tol <= 0.0) o.tol = 1e-14;
   if (o.check_every > 4096) o.check_every = 4096;
-  if ((int64_t)o.maxit + o.check_every + 2 > kMaxHistory) {
-    set_error("maxit %d too large (limit %d)", o.maxit, kMaxHistory - o.check_every - 2);
-    return FCT_EINVAL;
-  }
+  if (o.maxit > (1 << 30)) { set_error("maxit too large"); return FCT_EINVAL; }
+  const int P = p->nprob;
   CglsArgs a;
-  a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.ell = p->d_ell; a.rowmap = p->d_rowmap;
-  a.M = p->M; a.n = p->n; a.K = p->K;
+  a.rblk = p->d_rblk; a.cblk = p->d_cblk; a.prob = p->d_prob;
+  a.nrblk = p->nrblk; a.ncblk = p->ncblk; a.nprob = P;
+  a.ell = p->d_ell; a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.rowmap = p->d_rowmap;
   a.rq = ws->d_rq; a.ps = ws->d_ps; a.c = d_c;
   a.part_q = ws->d_part_q; a.part_s = ws->d_part_s;
-  a.hist_gamma = ws->d_hist_gamma; a.hist_alpha = ws->d_hist_alpha;
+  a.ring = ws->d_ring; a.gamma0 = ws->d_gamma0; a.done = ws->d_done; a.flags = ws->d_flags;
   a.state = ws->d_state; a.tol2 = o.tol * o.tol;
 
   FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
@@ -621,16 +840,16 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   }
 
   // Chunks of iterations are kept two deep in the stream: while chunk i
-  // runs, the host reads the convergence state copied after chunk i-1.
-  // From the observed decrease of ||A^T r||^2 the host predicts how many
-  // iterations remain and shortens the next chunk accordingly, so few
-  // (early-exiting) launches run after convergence.
-  struct Slot { int upto; };
-  Slot slots[2];
+  // runs, the host reads the per-problem convergence state copied after
+  // chunk i-1.  From each running problem's observed decrease of
+  // ||A^T r||^2 the host predicts how many iterations remain and shortens
+  // the next chunk accordingly, so few (early-exiting) launches run after
+  // the last problem has converged.
+  int upto[2] = {0, 0};
   int head = 0, inflight = 0, queued = 0;
-  int32_t stop = 0, breakdown = 0;
-  int kprev = -1, klast = -1;
-  double gprev = 0.0, glast = 0.0, g0seen = -1.0;
+  bool all_done = false;
+  std::vector<int> kprev((size_t)P, -1), klast((size_t)P, -1);
+  std::vector<double> gprev((size_t)P, 0.0), glast((size_t)P, 0.0);
   int target = o.maxit;
   while (true) {
     while (inflight < 2 && queued < o.maxit && queued < target) {
@@ -644,12 +863,12 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
       }
       queued += c;
       const int sl = (head + inflight) & 1;
-      slots[sl].upto = queued;
-      FCT_HIP(hipMemcpyAsync(ws->h_state + 4 * sl, ws->d_state, sizeof(int32_t) * 4,
+      upto[sl] = queued;
+      FCT_HIP(hipMemcpyAsync(ws->h_done + (size_t)sl * P, ws->d_done, sizeof(int32_t) * P,
                              hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(ws->h_gamma + 2 * sl, ws->d_hist_gamma + (queued - 1),
-                             sizeof(double), hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(ws->h_gamma + 2 * sl + 1, ws->d_hist_gamma, sizeof(double),
+      FCT_HIP(hipMemcpyAsync(ws->h_ring + (size_t)sl * 8 * P, ws->d_ring, sizeof(double) * 8 * P,
+                             hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipMemcpyAsync(ws->h_gamma0 + (size_t)sl * P, ws->d_gamma0, sizeof(double) * P,
                              hipMemcpyDeviceToHost, s));
       FCT_HIP(hipEventRecord(ws->ev[sl], s));
       ++inflight;
@@ -659,47 +878,94 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     FCT_HIP(hipEventSynchronize(ws->ev[sl]));
     head ^= 1;
     --inflight;
-    const int32_t* hs = ws->h_state + 4 * sl;
-    if (hs[0] != 0) { stop = hs[0]; breakdown = hs[2]; break; }
-    // rate estimate of ||A^T r_k||^2 and the iterations still needed
-    kprev = klast; gprev = glast;
-    klast = slots[sl].upto - 1;
-    glast = ws->h_gamma[2 * sl];
-    g0seen = ws->h_gamma[2 * sl + 1];
-    if (kprev >= 0 && glast > 0.0 && gprev > glast && g0seen > 0.0) {
-      const double lrate = (std::log(glast) - std::log(gprev)) / (double)(klast - kprev);
-      const double need = (std::log(a.tol2 * g0seen) - std::log(glast)) / lrate;
-      if (std::isfinite(need) && need >= 0.0) {
-        const double t = (double)klast + need + 2.0;
-        target = t < (double)o.maxit ? (int)t + 1 : o.maxit;
-        if (target <= queued) target = queued + 1;   // keep going one at a time
+    const int32_t* hd = ws->h_done + (size_t)sl * P;
+    const double* hr = ws->h_ring + (size_t)sl * 8 * P;
+    const double* hg0 = ws->h_gamma0 + (size_t)sl * P;
+    const int k = upto[sl] - 1;
+    all_done = true;
+    int need_max = -1;
+    for (int q = 0; q < P; ++q) {
+      if (hd[q] != 0) continue;
+      all_done = false;
+      kprev[q] = klast[q]; gprev[q] = glast[q];
+      klast[q] = k; glast[q] = hr[q * 8 + (k & 3)];
+      const double g0 = hg0[q];
+      if (kprev[q] >= 0 && glast[q] > 0.0 && gprev[q] > glast[q] && g0 > 0.0) {
+        const double lrate = (std::log(glast[q]) - std::log(gprev[q])) / (double)(k - kprev[q]);
+        const double need = (std::log(a.tol2 * g0) - std::log(glast[q])) / lrate;
+        if (std::isfinite(need) && need >= 0.0) {
+          const double t = (double)k + need + 2.0;
+          need_max = std::max(need_max, t < (double)o.maxit ? (int)t + 1 : o.maxit);
+        } else {
+          need_max = o.maxit;
+        }
+      } else {
+        need_max = o.maxit;
       }
     }
-    if (queued >= target && inflight == 0 && queued < o.maxit) target = queued + 1;
+    if (all_done) break;
+    target = std::max(need_max, queued + 1);
   }
   FCT_HIP(hipStreamSynchronize(s));
-  const int iters = stop ? stop - 1 : o.maxit;
-  if (!stop) FCT_HIP(launch_cgls_gamma(a, iters, s));
-  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[4], ws->d_hist_gamma, sizeof(double), hipMemcpyDeviceToHost, s));
-  FCT_HIP(hipMemcpyAsync(&ws->h_gamma[5], ws->d_hist_gamma + iters, sizeof(double), hipMemcpyDeviceToHost, s));
+  // final per-problem state (slot 2)
+  int32_t* fd = ws->h_done + (size_t)2 * P;
+  double* fr = ws->h_ring + (size_t)2 * 8 * P;
+  double* fg0 = ws->h_gamma0 + (size_t)2 * P;
+  FCT_HIP(hipMemcpyAsync(fd, ws->d_done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
   FCT_HIP(hipStreamSynchronize(s));
-  const double g0 = ws->h_gamma[4], gk = ws->h_gamma[5];
-  if (timing && iters > 0) {
+  bool any_running = false;
+  for (int q = 0; q < P; ++q) any_running |= fd[q] == 0;
+  if (any_running) FCT_HIP(launch_cgls_gamma(a, queued, s));
+  FCT_HIP(hipMemcpyAsync(fr, ws->d_ring, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipMemcpyAsync(fg0, ws->d_gamma0, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipMemcpyAsync(ws->h_flags, ws->d_flags, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipStreamSynchronize(s));
+
+  ws->last.assign((size_t)P, fct_solve_info());
+  fct_solve_info agg;
+  std::memset(&agg, 0, sizeof(agg));
+  agg.problems = P;
+  bool nonfinite = false;
+  int max_iter = 0;
+  for (int q = 0; q < P; ++q) {
+    fct_solve_info& r = ws->last[(size_t)q];
+    std::memset(&r, 0, sizeof(r));
+    const int it = fd[q] != 0 ? fd[q] - 1 : queued;
+    const double g0 = fg0[q], gk = fr[q * 8 + (it & 3)];
+    r.iterations = it;
+    r.converged = (fd[q] != 0 && ws->h_flags[q] == 0) ? 1 : 0;
+    r.normal_residual0 = std::sqrt(g0);
+    r.rel_normal_residual = g0 > 0 ? std::sqrt(gk / g0) : 0.0;
+    r.problems = 1;
+    r.problems_converged = r.converged;
+    if (!std::isfinite(g0)) nonfinite = true;
+    // a problem with A^T b = 0 has c = c_0 exact
+    if (fd[q] == 1 && g0 == 0.0) { r.converged = 1; r.problems_converged = 1; }
+    max_iter = std::max(max_iter, it);
+    agg.problems_converged += r.converged;
+    agg.rel_normal_residual = std::max(agg.rel_normal_residual, r.rel_normal_residual);
+    agg.normal_residual0 = std::max(agg.normal_residual0, r.normal_residual0);
+  }
+  agg.iterations = max_iter;
+  agg.converged = agg.problems_converged == P ? 1 : 0;
+
+  if (timing && max_iter > 0) {
     // Mean kernel times from back-to-back launches bracketed by HIP events
-    // on this stream, after the solve: the row kernel re-runs iteration
-    // iters-1 with the stop test disabled (it only rewrites r, q, the row
-    // partials and that iteration's history entry), then the column kernel
-    // runs with its coefficient
+    // on this stream, after the results were read: every problem re-runs
+    // iteration max_iter-1 (stop test off, its own stop flags untouched),
+    // first the row kernel, then the column kernel with its coefficient
     // update directed into scratch, so d_c keeps the solution.
     constexpr int kReps = 200;
     CglsArgs t = a;
     t.tol2 = 0.0;
     t.c = ws->d_ctmp;
-    const int kt = iters - 1;
-    hipEvent_t ev[3];
+    t.done = ws->d_done_tmp;
+    t.state = ws->d_state_tmp;
+    FCT_HIP(launch_fill_i32(ws->d_done_tmp, P, 0, s));
+    FCT_HIP(launch_cgls_set_base(ws->d_state_tmp, max_iter - 1, s));
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    struct EG { hipEvent_t* e; ~EG() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } eg{ev};
     for (auto& e : ev) FCT_HIP(hipEventCreate(&e));
-    struct EG { hipEvent_t* e; ~EG() { for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]); } } eg{ev};
-    FCT_HIP(launch_cgls_timing_state(ws->d_state, kt, s));
     FCT_HIP(hipEventRecord(ev[0], s));
     for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_rows(t, 0, s));
     FCT_HIP(hipEventRecord(ev[1], s));
@@ -709,27 +975,26 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     float m1 = 0.f, m2 = 0.f;
     FCT_HIP(hipEventElapsedTime(&m1, ev[0], ev[1]));
     FCT_HIP(hipEventElapsedTime(&m2, ev[1], ev[2]));
-    if (info) {
-      info->rows_kernel_us = 1e3 * m1 / kReps;
-      info->cols_kernel_us = 1e3 * m2 / kReps;
-    }
-    FCT_HIP(launch_cgls_timing_state_restore(ws->d_state, stop, breakdown, s));
-    FCT_HIP(hipStreamSynchronize(s));
+    agg.rows_kernel_us = 1e3 * m1 / kReps;
+    agg.cols_kernel_us = 1e3 * m2 / kReps;
   }
-  const bool conv = stop && !breakdown;
-  if (info) {
-    if (!timing) { info->rows_kernel_us = 0.0; info->cols_kernel_us = 0.0; }
-    info->iterations = iters;
-    info->converged = conv ? 1 : 0;
-    info->normal_residual0 = std::sqrt(g0);
-    info->rel_normal_residual = g0 > 0 ? std::sqrt(gk / g0) : 0.0;
-  }
-  if (!std::isfinite(g0)) { set_error("||A^T b|| is not finite"); return FCT_ENONFINITE; }
-  if (!conv && g0 > 0) {
-    set_error("CGLS stopped after %d iterations at relative normal residual %.3e%s", iters,
-              g0 > 0 ? std::sqrt(gk / g0) : 0.0, breakdown ? " (breakdown)" : "");
+  if (info) *info = agg;
+  if (nonfinite) { set_error("||A^T b|| is not finite"); return FCT_ENONFINITE; }
+  if (!agg.converged) {
+    set_error("CGLS: %d of %d problems did not converge within %d iterations "
+              "(largest relative normal residual %.3e)", P - agg.problems_converged, P, queued,
+              agg.rel_normal_residual);
     return FCT_ENOCONV;
   }
+  return FCT_OK;
+}
+
+fct_status fct_ws_problem_info(const fct_ws* w, int32_t q, fct_solve_info* out) {
+  if (!w || !out || q < 0 || q >= (int32_t)w->last.size()) {
+    set_error("bad workspace, problem index or no solve yet");
+    return FCT_EINVAL;
+  }
+  *out = w->last[(size_t)q];
   return FCT_OK;
 }
 

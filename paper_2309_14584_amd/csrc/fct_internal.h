@@ -87,7 +87,8 @@ hipError_t launch_ell(const int32_t* seg_off, const int32_t* perm, int64_t M, in
                       hipStream_t s);
 
 // DCT passes
-hipError_t launch_dct_level(const DctLevel& lv, const double* in, double* scratch,
+// mode: fct_dct_mode; scratch holds doubles (FP64) or floats (other modes)
+hipError_t launch_dct_level(const DctLevel& lv, int mode, const double* in, void* scratch,
                             double* out, const double* mats, const int64_t* bin_id,
                             hipStream_t s);
 
@@ -100,28 +101,68 @@ hipError_t launch_sample(int family, const SampleParams& prm, int D, int K,
                          int64_t total_points, const double* nodes, double* out,
                          hipStream_t s);
 
+// Work decomposition of the CGLS kernels.  A plan holds one or more
+// independent problems (a batch); every workgroup of the row (column)
+// kernel covers up to kBlock rows (columns) of a single problem.
+struct RowBlock {
+  int32_t prob;       // problem index
+  int32_t row0;       // first global row of the block
+  int32_t row_end;    // one past the last row of the block
+  int32_t cblk_off;   // the problem's column blocks [cblk_off, cblk_off + ncblk)
+  int32_t ncblk;
+  int32_t first;      // 1 for the problem's first row block (writes its scalars)
+  int32_t pad0, pad1;
+};
+struct ColBlock {
+  int32_t prob;
+  int32_t col0;       // first global column of the block
+  int32_t col_end;
+  int32_t col_off;    // first global column of the problem
+  int32_t rblk_off;   // the problem's row blocks
+  int32_t nrblk;
+  int32_t K;          // grids of the problem
+  int32_t n;          // columns of the problem
+  int32_t rmap_off;   // offset of the problem's rowmap block [K][n]
+  int32_t first;
+  int32_t pad0, pad1;
+};
+struct ProbInfo {
+  int32_t row_off, M;     // global rows of the problem
+  int32_t col_off, n;     // global columns
+  int32_t K, rmap_off;    // grids, rowmap (and perm) offset
+  int32_t rblk_off, nrblk;
+  int32_t cblk_off, ncblk;
+  int32_t grid_off;       // first grid of the problem
+  int32_t pad0;
+};
+
 // operator
 hipError_t launch_apply_A(const int32_t* seg_off, const int32_t* perm, int64_t M,
                           const double* c, double* q, hipStream_t s);
-hipError_t launch_apply_AT(const int32_t* rowmap, int K, int64_t n, const double* r,
-                           double* out, hipStream_t s);
+hipError_t launch_apply_AT(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
+                           const double* r, double* out, hipStream_t s);
 
 // CGLS
 struct CglsArgs {
+  const RowBlock* rblk;
+  const ColBlock* cblk;
+  const ProbInfo* prob;
+  int64_t nrblk, ncblk;
+  int32_t nprob;
+  const int4* ell;    // [M] first four columns of each row (see plan)
   const int32_t* seg_off;
   const int32_t* perm;
-  const int4* ell;    // [M] first four columns of each row (see plan)
   const int32_t* rowmap;
-  int64_t M, n;
-  int32_t K;
   double2* rq;        // [M] (r, q) per row
   double2* ps;        // [n] (p, s) per column
   double* c;          // [n]
-  double* part_q;     // [nblocks rows]
-  double* part_s;     // [nblocks cols]
-  double* hist_gamma; // [kMaxHistory]
-  double* hist_alpha; // [kMaxHistory]
-  int32_t* state;     // [0] done flag (iteration+1), [1] iteration base
+  double* part_q;     // [nrblk]
+  double* part_s;     // [ncblk]
+  double* ring;       // [nprob][8]: gamma ring (k mod 4), alpha ring (k mod 4)
+  double* gamma0;     // [nprob] ||A^T r_0||^2
+  int32_t* done;      // [nprob] iteration+1 at which the problem stopped, 0 while running
+  int32_t* flags;     // [nprob] 1 = breakdown (A p = 0)
+  int32_t* state;     // [0] iteration base
   double tol2;
 };
 hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipStream_t s);
@@ -129,15 +170,18 @@ hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s);
 hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s);
 hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s);
 hipError_t launch_cgls_advance(int32_t* state, int chunk, hipStream_t s);
-// hist_gamma[k] = ||s||^2 from the current column partials
+// ring entry k = ||s||^2 of the current column partials, for running problems
 hipError_t launch_cgls_gamma(const CglsArgs& a, int k, hipStream_t s);
-// timing support: state = (running, base k); then back to the recorded stop
-hipError_t launch_cgls_timing_state(int32_t* state, int k, hipStream_t s);
-hipError_t launch_cgls_timing_state_restore(int32_t* state, int stop, int breakdown,
-                                            hipStream_t s);
+hipError_t launch_cgls_set_base(int32_t* state, int base, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* v, int n, int value, hipStream_t s);
 int64_t segment_blocks(int64_t L);
-int64_t cgls_row_blocks(int64_t M);
-int64_t cgls_col_blocks(int64_t n);
+
+// batch construction: dst[i] = src[i] + add (i < count)
+hipError_t launch_copy_add_i32(int32_t* dst, const int32_t* src, int64_t count, int32_t add,
+                               hipStream_t s);
+// ELL entries shifted to global columns (col_add) and perm positions (perm_add)
+hipError_t launch_copy_ell(int4* dst, const int4* src, int64_t count, int32_t col_add,
+                           int32_t perm_add, hipStream_t s);
 
 }  // namespace fct
 
@@ -145,28 +189,38 @@ int64_t cgls_col_blocks(int64_t n);
 
 struct fct_plan {
   int device = 0;
-  int32_t D = 0, K = 0;
-  int64_t n = 0;
-  int64_t M = 0;
+  int32_t nprob = 1;               // problems (1, or the size of a batch)
+  int32_t D = 0;                   // dimension (largest over a batch)
+  int32_t K = 0;                   // grids over all problems
+  int64_t n = 0;                   // columns over all problems
+  int64_t M = 0;                   // rows over all problems
   int64_t total_points = 0;
   int64_t max_points = 0;
   int32_t maxdeg = 0;
-  std::vector<int32_t> grids;      // [K][D]
+  std::vector<int32_t> grid_D;     // [K] dimension of each grid's problem
+  std::vector<int64_t> grid_goff;  // [K+1] offsets of each grid's degrees in `grids`
+  std::vector<int32_t> grids;      // degrees, grid after grid
   std::vector<int64_t> points;     // [K]
   std::vector<int64_t> point_off;  // [K+1]
   std::vector<int32_t> row_off;    // [K+1]
+  std::vector<fct::ProbInfo> probs;      // [nprob]
+  std::vector<int64_t> prob_point_off;   // [nprob+1]
+  int64_t nrblk = 0, ncblk = 0;
 
-  int32_t* d_support = nullptr;    // [n][D]
-  int32_t* d_grids = nullptr;      // [K][D]
-  int64_t* d_strides = nullptr;    // [K][D]
+  int32_t* d_support = nullptr;    // [n][D]      (single problem only)
+  int64_t* d_strides = nullptr;    // [K][D]      (single problem only)
+  int64_t* d_alias = nullptr;      // [K*n]       (single problem only)
+  int32_t* d_grids = nullptr;      // degrees, as `grids`
   int64_t* d_point_off = nullptr;  // [K+1]
-  int64_t* d_alias = nullptr;      // [K*n]
-  int32_t* d_perm = nullptr;       // [K*n]
-  int32_t* d_seg_off = nullptr;    // [M+1]
+  int32_t* d_perm = nullptr;       // [sum K n]   global columns
+  int32_t* d_seg_off = nullptr;    // [M+1]       offsets into perm
   int64_t* d_bin_id = nullptr;     // [M]
-  int32_t* d_rowmap = nullptr;     // [K*n]
+  int32_t* d_rowmap = nullptr;     // [sum K n]   global rows, block [K_p][n_p] per problem
   int32_t* d_row_off = nullptr;    // [K+1]
   int4* d_ell = nullptr;           // [M]
+  fct::RowBlock* d_rblk = nullptr; // [nrblk]
+  fct::ColBlock* d_cblk = nullptr; // [ncblk]
+  fct::ProbInfo* d_prob = nullptr; // [nprob]
   double* d_nodes = nullptr;       // [(maxdeg+1) * 64]
   double* d_cmat = nullptr;        // packed forward DCT-I matrices, degrees 0..maxdeg
   double* d_emat = nullptr;        // packed evaluation matrices
@@ -183,19 +237,26 @@ struct fct_ws {
   double2* d_rq = nullptr;         // [M]
   double2* d_ps = nullptr;         // [n]
   double* d_ctmp = nullptr;        // [n] coefficient sink of timing launches
-  double* d_part_q = nullptr;
-  double* d_part_s = nullptr;
-  double* d_hist_gamma = nullptr;
-  double* d_hist_alpha = nullptr;
-  double* d_params = nullptr;      // [2 * FCT_MAX_DIM + 8] sampler parameters
+  double* d_part_q = nullptr;      // [nrblk]
+  double* d_part_s = nullptr;      // [ncblk]
+  double* d_ring = nullptr;        // [nprob][8]
+  double* d_gamma0 = nullptr;      // [nprob]
+  int32_t* d_done = nullptr;       // [nprob]
+  int32_t* d_flags = nullptr;      // [nprob]
+  int32_t* d_done_tmp = nullptr;   // [nprob] (timing launches)
   int32_t* d_state = nullptr;      // [4]
-  int32_t* h_state = nullptr;      // pinned [2][4]: state copies of two in-flight chunks
-  double* h_gamma = nullptr;       // pinned [6]: per chunk (gamma_last, gamma_0), then final pair
+  int32_t* d_state_tmp = nullptr;  // [4]   (timing launches)
+  // pinned host copies: two in-flight chunk checks, then the final state
+  int32_t* h_done = nullptr;       // [3][nprob]
+  double* h_ring = nullptr;        // [3][nprob][8]
+  double* h_gamma0 = nullptr;      // [3][nprob]
+  int32_t* h_flags = nullptr;      // [nprob]
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;
   int graph_chunk = 0;
-  const double* graph_b = nullptr;
   double* graph_c = nullptr;
   double graph_tol2 = -1.0;
+  // per-problem results of the last solve
+  std::vector<fct_solve_info> last;
 };

@@ -265,7 +265,45 @@ __global__ __launch_bounds__(kBlock) void ell_kernel(const int32_t* __restrict__
   ell[r] = e;
 }
 
+__global__ __launch_bounds__(kBlock) void copy_add_kernel(int32_t* __restrict__ dst,
+                                                          const int32_t* __restrict__ src,
+                                                          int64_t count, int32_t add) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i] + add;
+}
+
+__global__ __launch_bounds__(kBlock) void copy_ell_kernel(int4* __restrict__ dst,
+                                                          const int4* __restrict__ src,
+                                                          int64_t count, int32_t col_add,
+                                                          int32_t perm_add) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int4 e = src[i];
+  e.x = e.x >= 0 ? e.x + col_add : e.x;
+  e.y = e.y >= 0 ? e.y + col_add : e.y;
+  e.z = e.z >= 0 ? e.z + col_add : e.z;
+  // -1: empty; <= -2: continuation -(2 + t) at perm position t
+  e.w = e.w >= 0 ? e.w + col_add : (e.w <= -2 ? e.w - perm_add : e.w);
+  dst[i] = e;
+}
+
 }  // namespace
+
+hipError_t launch_copy_add_i32(int32_t* dst, const int32_t* src, int64_t count, int32_t add,
+                               hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_add_kernel, dim3((unsigned)ceil_div(count, kBlock)), dim3(kBlock), 0, s,
+                     dst, src, count, add);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_ell(int4* dst, const int4* src, int64_t count, int32_t col_add,
+                           int32_t perm_add, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_ell_kernel, dim3((unsigned)ceil_div(count, kBlock)), dim3(kBlock), 0, s,
+                     dst, src, count, col_add, perm_add);
+  return hipGetLastError();
+}
 
 hipError_t launch_ell(const int32_t* seg_off, const int32_t* perm, int64_t M, int4* ell,
                       hipStream_t s) {

@@ -29,7 +29,7 @@ FCT_OK, FCT_EINVAL, FCT_ENOMEM, FCT_EDEVICE, FCT_ERANK, FCT_ENOCONV, FCT_ENONFIN
 FCT_PLAN_ALLOW_RANK_DEFICIENT = 1
 
 FAMILY_PLANTED, FAMILY_EXPCOS, FAMILY_GAUSS, FAMILY_RUNGE, FAMILY_OSC = range(5)
-DCT_F64 = 0
+DCT_F64, DCT_F32, DCT_BF16X3 = 0, 1, 2
 SOLVE_F64 = 0
 
 _vp = ctypes.c_void_p
@@ -39,7 +39,8 @@ _i32, _i64, _u32, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes
 class PlanInfo(ctypes.Structure):
     _fields_ = [("D", _i32), ("K", _i32), ("n_support", _i64), ("total_points", _i64),
                 ("total_rows", _i64), ("max_points", _i64), ("max_degree", _i32),
-                ("dct_levels", _i32), ("device_bytes", _i64)]
+                ("dct_levels", _i32), ("device_bytes", _i64), ("problems", _i32),
+                ("reserved", _i32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -51,7 +52,8 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32),
                 ("rel_normal_residual", _dbl), ("normal_residual0", _dbl),
-                ("rows_kernel_us", _dbl), ("cols_kernel_us", _dbl)]
+                ("rows_kernel_us", _dbl), ("cols_kernel_us", _dbl),
+                ("problems", _i32), ("problems_converged", _i32)]
 
 
 def _sig(name, res, *args):
@@ -79,13 +81,18 @@ _dct = _sig("fct_dct", ctypes.c_int, _vp, _vp, _vp, _i32, _vp, _vp)
 _dct_full = _sig("fct_dct_full", ctypes.c_int, _vp, _vp, _vp, _i32, _vp, _vp)
 _apply_A = _sig("fct_apply_A", ctypes.c_int, _vp, _vp, _vp, _vp)
 _apply_AT = _sig("fct_apply_AT", ctypes.c_int, _vp, _vp, _vp, _vp)
+_batch_create = _sig("fct_batch_create", ctypes.c_int, _i32, ctypes.POINTER(_vp), _vp,
+                     ctypes.POINTER(_vp))
+_plan_problem = _sig("fct_plan_problem", ctypes.c_int, _vp, _i32, *[ctypes.POINTER(_i64)] * 6)
+_ws_problem_info = _sig("fct_ws_problem_info", ctypes.c_int, _vp, _i32, ctypes.POINTER(SolveInfo))
 _solve = _sig("fct_solve", ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
               ctypes.POINTER(SolveInfo), _vp, _vp)
 
 EXPORTED = ["fct_last_error", "fct_status_string", "fct_abi_version", "fct_plan_create",
             "fct_plan_destroy", "fct_plan_get_info", "fct_plan_grid", "fct_plan_export",
             "fct_grid_nodes", "fct_ws_create", "fct_ws_destroy", "fct_sample", "fct_dct",
-            "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve"]
+            "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve", "fct_batch_create",
+            "fct_plan_problem", "fct_ws_problem_info"]
 
 
 class FctError(RuntimeError):
@@ -134,12 +141,20 @@ class SolveResult:
     status: int
     rows_kernel_us: float = 0.0
     cols_kernel_us: float = 0.0
+    problems: int = 1
+    problems_converged: int = 0
 
 
 class Plan:
     """Alias structure of a support on K Lobatto grids (fct_plan_create)."""
 
-    def __init__(self, support, grids, allow_rank_deficient=False, stream=None):
+    def __init__(self, support=None, grids=None, allow_rank_deficient=False, stream=None,
+                 _handle=None):
+        if _handle is not None:
+            self._h = _handle
+            self.support = self.grids = None
+            self._load_info()
+            return
         S = np.ascontiguousarray(np.asarray(support, dtype=np.int32))
         G = np.ascontiguousarray(np.asarray(grids, dtype=np.int32))
         if S.ndim != 2 or G.ndim != 2 or S.shape[1] != G.shape[1]:
@@ -150,12 +165,36 @@ class Plan:
         _check(_plan_create(S.shape[1], S.shape[0], S.ctypes.data_as(_vp), G.shape[0],
                             G.ctypes.data_as(_vp), flags, _stream(stream), ctypes.byref(h)))
         self._h = h
+        self._load_info()
+
+    def _load_info(self):
         info = PlanInfo()
-        _check(_plan_get_info(h, ctypes.byref(info)))
+        _check(_plan_get_info(self._h, ctypes.byref(info)))
         self.info = info
         self.D, self.K, self.n = info.D, info.K, info.n_support
         self.M, self.P = info.total_rows, info.total_points
+        self.problems = info.problems
         self._ws = None
+
+    @classmethod
+    def batch(cls, plans, stream=None):
+        """Pack single-problem plans into one batch plan (fct_batch_create)."""
+        arr = (_vp * len(plans))(*[p._h for p in plans])
+        h = _vp()
+        _check(_batch_create(len(plans), arr, _stream(stream), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def problem(self, q):
+        """(n, rows, col_offset, row_offset, point_offset, points) of problem q."""
+        vals = [_i64() for _ in range(6)]
+        _check(_plan_problem(self._h, q, *[ctypes.byref(v) for v in vals]))
+        return tuple(v.value for v in vals)
+
+    def problem_result(self, q):
+        info = SolveInfo()
+        _check(_ws_problem_info(self.ws, q, ctypes.byref(info)))
+        return SolveResult(info.iterations, bool(info.converged), info.rel_normal_residual,
+                           info.normal_residual0, FCT_OK, 0.0, 0.0, 1, info.problems_converged)
 
     def close(self):
         if self._ws is not None:
@@ -227,7 +266,7 @@ class Plan:
                     _ptr(out, torch.float64, self.M, "out"), mode, self.ws, _stream(stream)))
         return out
 
-    def dct_full(self, samples, out=None, mode=DCT_F64, stream=None):
+    def dct_full(self, samples, out=None, mode=DCT_F64, stream=None):  # noqa: D401
         torch = _torch()
         out = self._empty(self.P) if out is None else out
         _check(_dct_full(self._h, _ptr(samples, torch.float64, self.P, "samples"),
@@ -264,4 +303,5 @@ class Plan:
             _check(st)
         return out, SolveResult(info.iterations, bool(info.converged),
                                 info.rel_normal_residual, info.normal_residual0, st,
-                                info.rows_kernel_us, info.cols_kernel_us)
+                                info.rows_kernel_us, info.cols_kernel_us, info.problems,
+                                info.problems_converged)

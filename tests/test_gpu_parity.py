@@ -210,3 +210,34 @@ def test_solve_warm_start_and_limits(fct):
         plan.solve(bad)
     assert ei.value.status == fct.FCT_ENONFINITE
     plan.close()
+
+
+# Reduced-precision DCT modes: error bound per axis ~ e * unit roundoff of
+# the mode (FP32: 2^-24 per product and sum; split-BF16x3: the dropped
+# C_lo x_lo term and the bf16 rounding of the low parts, ~2^-16 relative per
+# product, plus FP32 sums); summed over the D axes, relative to the largest
+# magnitude.
+MODE_EPS = {1: 2.0 ** -24, 2: 2.0 ** -15}
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["f32", "bf16x3"])
+@pytest.mark.parametrize("prob", [p for p in CASES if int(p.grids.max()) <= 31] + [W.config2()],
+                         ids=[p.name for p in CASES if int(p.grids.max()) <= 31] + ["cfg2"])
+def test_dct_reduced_precision(fct, prob, mode):
+    rng = np.random.default_rng(13)
+    plan = _plan(fct, prob)
+    ref_plan = O.build_plan(prob.support, prob.grids)
+    x = rng.standard_normal(plan.P)
+    offs = np.concatenate([[0], np.cumsum(prob.points)])
+    ref_full = [O.dct_grid(x[offs[l]:offs[l + 1]], prob.grids[l]) for l in range(prob.K)]
+    ref_b = O.rhs_from_transforms(ref_plan, ref_full)
+    b = _host(plan.dct(_dev(x), mode=mode))
+    emax = int(prob.grids.max()) + 1
+    bound = 4.0 * prob.D * emax * MODE_EPS[mode] * np.max(np.abs(x)) / max(np.max(np.abs(ref_b)), 1e-300)
+    err = _rel(b, ref_b)
+    print(f"mode {mode}: rel err {err:.2e} (bound {bound:.2e})")
+    assert err < bound
+    # and the same bits through the full-tensor entry point at the kept bins
+    full = _host(plan.dct_full(_dev(x), mode=mode))
+    assert _rel(full, np.concatenate(ref_full)) < bound
+    plan.close()

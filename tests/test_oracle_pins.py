@@ -311,6 +311,8 @@ def test_least_squares_methods_agree_inconsistent():
     c_sv = np.linalg.lstsq(O.dense_A(plan), b, rcond=None)[0]
     assert O.max_rel_err(c_qr, c_sv) < 1e-12
     assert O.max_rel_err(c_ne, c_sv) < 1e-12
+    c_ls, _, _ = O.lstsq_lsqr(plan, b)
+    assert O.max_rel_err(c_ls, c_sv) < 1e-10
     assert np.abs(O.normal_residual(plan, b, c_qr)).max() < 1e-13 * np.abs(b).max()
     # the system is inconsistent: the residual itself is not zero
     assert np.linalg.norm(b - O.dense_A(plan) @ c_qr) > 1e-8
@@ -385,3 +387,36 @@ def test_analytic_families_special_points():
     assert abs(f2[13] - math.exp(-0.14 / 1.28)) < 1e-15
     f4 = O.sample_function(4, [], [2, 2, 2])
     assert abs(f4[13] - (math.sin(3 * math.cos(3.0)) + 1.0)) < 1e-14
+
+
+def test_batched_workload_instances():
+    """The 256-problem batch: sizes within the cap, every problem passes the
+    rank pre-check, and a sample of the small ones is full rank with
+    kappa(A) <= 1e4 (Alg. 2's stopping rule)."""
+    with open(os.path.join(GOLDEN, "cfg3_extra_grids.json")) as fh:
+        extra = json.load(fh)["extra_grids"]
+    probs = W.config3(extra_grids=extra)
+    assert len(probs) == 256
+    assert all(p.n <= 50_000 and 3 <= p.D <= 8 for p in probs)
+    assert all(p.K >= 6 * p.D and p.total_points >= 2 * p.n for p in probs)
+    assert all(O.fold_injective(p.support, p.grids) for p in probs)
+    small = [p for p in probs if p.n <= 1000][:8]
+    assert small
+    for p in small:
+        full, kappa = O.rank_check(O.build_plan(p.support, p.grids))
+        assert full and kappa <= 1e4
+
+
+@pytest.mark.slow
+def test_batched_workload_selected_grids_recover():
+    """Alg. 2 as run by tests/golden/make_cfg3_grids.py: the problem that
+    needed extra grids, and one that did not, are recovered exactly by the
+    oracle's LSQR (consistent system, full column rank)."""
+    with open(os.path.join(GOLDEN, "cfg3_extra_grids.json")) as fh:
+        extra = json.load(fh)["extra_grids"]
+    probs = W.config3(extra_grids=extra)
+    for i in [int(k) for k in extra][:1] + [0]:
+        p = probs[i]
+        plan = O.build_plan(p.support, p.grids)
+        c, its, _ = O.lstsq_lsqr(plan, O.sparse_A(plan) @ p.coeffs)
+        assert O.max_rel_err(c, p.coeffs) < 1e-10

@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "total_degree_support", "euclidean_degree_support", "grid_points",
     "draw_grids_uniform", "draw_grid_capped", "planted_coefficients",
-    "Problem", "config1", "config2", "small_problem", "streams",
+    "Problem", "config1", "config2", "config3", "config3_problem", "small_problem", "streams",
     "FAMILY_PLANTED", "FAMILY_EXPCOS", "FAMILY_GAUSS", "FAMILY_RUNGE",
     "FAMILY_OSC",
 ]
@@ -111,17 +111,17 @@ def draw_grids_uniform(rng, D, lo, hi, n_support, oversample, min_grids=1,
     return np.ascontiguousarray(np.array(grids, dtype=np.int32))
 
 
-def draw_grid_capped(rng, D, lo, hi, cap):
+def draw_grid_capped(rng, D, lo, hi, cap, rest=0):
     """One grid drawn the way the sampling-rate selection (Alg. 1) draws it.
 
     Dimensions are visited in a random order; each gets a degree drawn from
     ``U{lo..hi}``; once the running point count exceeds ``cap`` every
-    remaining dimension gets a single node (degree 0).  Degrees here are
-    Lobatto degrees, so the algorithm's draw of 1..d+1 *points* is a draw of
-    0..d here.
+    remaining dimension gets degree ``rest`` (0: a single node, as in the
+    algorithm).  Degrees here are Lobatto degrees, so the algorithm's draw of
+    1..d+1 *points* is a draw of 0..d here.
     """
     order = rng.permutation(D)
-    g = np.zeros(D, dtype=np.int64)
+    g = np.full(D, rest, dtype=np.int64)
     prod = 1
     for i in order:
         g[i] = rng.integers(lo, hi + 1)
@@ -132,10 +132,10 @@ def draw_grid_capped(rng, D, lo, hi, cap):
 
 
 def draw_grids_capped(rng, D, lo, hi, n_support, oversample, min_grids=1,
-                      max_grids=4096):
+                      max_grids=4096, rest=0):
     grids, total = [], 0
     while (total < oversample * n_support or len(grids) < min_grids):
-        g = draw_grid_capped(rng, D, lo, hi, n_support)
+        g = draw_grid_capped(rng, D, lo, hi, n_support, rest)
         grids.append(g)
         total += grid_points(g)
         if len(grids) >= max_grids:
@@ -231,3 +231,48 @@ def small_problem(seed: int, D: int, d: int, lo: int, hi: int, K: int,
     elif family == FAMILY_RUNGE:
         params = np.array([10.0])
     return Problem(f"small_D{D}_d{d}_K{K}_s{seed}", S, grids, family, params, c, seed)
+
+
+def config3_problem(rng_grid, rng_coef, cap=50_000):
+    """One problem of the batched workload: D ~ U{3..8}, d ~ U{6..16}, d
+    lowered until C(D+d, d) <= cap; grids drawn as in Alg. 1 (dimensions in
+    random order, degrees U{1..d}, once the running point count exceeds |S|
+    the remaining dimensions get degree 1) until the points reach 2|S| and
+    there are at least 6D grids; planted polynomial.
+
+    Two departures from Alg. 1 keep the seeded problems well posed: a
+    dimension beyond the cap gets two Lobatto nodes instead of one (a single
+    node leaves it entirely unresolved, which made a share of the problems
+    rank deficient), and 6D grids instead of the paper's 3D."""
+    D = int(rng_grid.integers(3, 9))
+    d = int(rng_grid.integers(6, 17))
+    while math.comb(D + d, d) > cap:
+        d -= 1
+    S = total_degree_support(D, d)
+    grids = draw_grids_capped(rng_grid, D, 1, d, len(S), 2.0, min_grids=6 * D, rest=1)
+    c = planted_coefficients(rng_coef, S)
+    return Problem(f"cfg3_D{D}_d{d}", S, grids, FAMILY_PLANTED, np.zeros(0), c)
+
+
+def config3(seed: int = 2, count: int = 256, extra_grids=None):
+    """The batched workload: `count` independent problems (config3_problem).
+
+    ``extra_grids`` maps a problem index to a number of further grids to
+    append (drawn by the same rule from a stream of their own): the output of
+    the grid-count selection (Alg. 2) that the oracle runs once and stores
+    under tests/golden/."""
+    g_grid, g_coef, _ = streams(seed)
+    g_more = np.random.default_rng(np.random.SeedSequence(seed).spawn(4)[3])
+    out = []
+    for i in range(count):
+        p = config3_problem(g_grid, g_coef)
+        p.name = f"{p.name}_{i}"
+        p.seed = seed
+        out.append(p)
+    for i in sorted(int(k) for k in (extra_grids or {})):
+        p = out[i]
+        d = int(p.support.max())
+        more = [draw_grid_capped(g_more, p.D, 1, d, p.n, 1)
+                for _ in range(int(extra_grids[str(i)] if str(i) in extra_grids else extra_grids[i]))]
+        p.grids = np.ascontiguousarray(np.concatenate([p.grids, np.array(more, dtype=np.int32)]))
+    return out
