@@ -88,7 +88,14 @@ typedef enum fct_dct_mode {
 
 /* Arithmetic of the least-squares solve. */
 typedef enum fct_solve_mode {
-  FCT_SOLVE_F64 = 0  /* CGLS in FP64 throughout */
+  FCT_SOLVE_F64 = 0,        /* CGLS in FP64 throughout */
+  FCT_SOLVE_F32_REFINE = 1, /* rounds of conjugate gradients on the normal equations
+                               with FP32 vectors (q, p, s) and FP64 inner products,
+                               each started from s = A^T (b - A c) computed in FP64
+                               for the FP64 iterate c (iterative refinement, which
+                               converges for inconsistent systems too); stops on the
+                               FP64 normal residual */
+  FCT_SOLVE_F32 = 2         /* a single such round, to tol (default 2e-7) */
 } fct_solve_mode;
 
 /* Plan creation flags. */
@@ -109,6 +116,7 @@ typedef struct fct_plan_info {
   int64_t device_bytes;   /* device memory held by the plan */
   int32_t problems;       /* 1, or the number of problems of a batch plan */
   int32_t reserved;
+  int64_t entries;        /* nonzeros of A: sum over problems of K * n_support */
 } fct_plan_info;
 
 typedef struct fct_solve_opts {
@@ -121,7 +129,12 @@ typedef struct fct_solve_opts {
                            the row kernel and of the column kernel with HIP events on
                            `stream` and report the means in fct_solve_info (d_c is
                            left as solved) */
-  double tol;           /* stop when ||A^T r||_2 <= tol ||A^T r_0||_2; 0 selects 1e-14 */
+  double tol;           /* stop when ||A^T r||_2 <= tol ||A^T r_0||_2; 0 selects 1e-14
+                           (2e-7 for FCT_SOLVE_F32) */
+  int32_t max_refine;   /* FCT_SOLVE_F32_REFINE: most rounds; 0 selects 12 */
+  int32_t reserved;
+  double inner_tol;     /* FCT_SOLVE_F32_REFINE: per-round reduction of the FP32
+                           normal residual; 0 selects 1e-5 */
 } fct_solve_opts;
 
 typedef struct fct_solve_info {
@@ -133,6 +146,8 @@ typedef struct fct_solve_info {
   double cols_kernel_us;      /* timing mode: mean time of one column-kernel launch (A^T r) */
   int32_t problems;           /* problems solved */
   int32_t problems_converged; /* problems that met the tolerance */
+  int32_t refinements;        /* FP32 rounds (largest over problems; 0 in FP64 mode) */
+  int32_t reserved;
 } fct_solve_info;
 
 /* ---- errors ------------------------------------------------------------ */

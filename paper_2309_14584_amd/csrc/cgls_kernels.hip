@@ -78,6 +78,17 @@ __device__ __forceinline__ double ring_alpha(const double* ring, int p, int k) {
   return ring[p * 8 + 4 + (k & 3)];
 }
 
+// (x, y) pairs stored in FP64 (double2) or FP32 (float2); arithmetic in FP64.
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+template <typename P> __device__ __forceinline__ P make_pair(double x, double y);
+template <> __device__ __forceinline__ double2 make_pair<double2>(double x, double y) {
+  return make_double2(x, y);
+}
+template <> __device__ __forceinline__ float2 make_pair<float2>(double x, double y) {
+  return make_float2((float)x, (float)y);
+}
+
 __global__ __launch_bounds__(kBlock) void apply_A_kernel(const int32_t* __restrict__ seg_off,
                                                          const int32_t* __restrict__ perm,
                                                          int64_t M, const double* __restrict__ c,
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void cgls_init_rows_kernel(CglsArgs a,
     const int32_t t1 = a.seg_off[row + 1];
     for (int32_t t = a.seg_off[row]; t < t1; ++t) acc += a.c[a.perm[t]];
   }
-  a.rq[row] = make_double2(b[row] - acc, 0.0);
+  static_cast<double2*>(a.rq)[row] = make_double2(b[row] - acc, 0.0);
 }
 
 // s_0 = A^T r_0, p = 0, c = 0 unless warm, partials of ||s_0||^2.
@@ -129,8 +140,9 @@ __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int 
   double sv = 0.0;
   if (j < bd.col_end) {
     const int32_t jl = j - bd.col_off;
-    for (int l = 0; l < bd.K; ++l) sv += a.rq[a.rowmap[bd.rmap_off + l * bd.n + jl]].x;
-    a.ps[j] = make_double2(0.0, sv);
+    const double2* rq = static_cast<const double2*>(a.rq);
+    for (int l = 0; l < bd.K; ++l) sv += rq[a.rowmap[bd.rmap_off + l * bd.n + jl]].x;
+    static_cast<double2*>(a.ps)[j] = make_double2(0.0, sv);
     if (!warm) a.c[j] = 0.0;
   }
   const double part = block_sum(sv * sv, sh);
@@ -141,8 +153,16 @@ __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int 
 // are known; further grids continue in a loop.
 constexpr int kPrefetch = 4;
 
+// NR: the normal-equation form used by the mixed-precision rounds.  The
+// residual r is not carried; the column kernel updates s = A^T r by
+// s <- s - alpha A^T q, so a round can start from s = A^T (b - A c)
+// computed in FP64, which tends to zero at the least-squares solution even
+// when the system is inconsistent (r itself does not).
+template <typename P, bool NR>
 __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) {
   __shared__ double sh[16];
+  P* const rqv = static_cast<P*>(a.rq);
+  const P* const psv = static_cast<const P*>(a.ps);
   __shared__ int s_done;
   const RowBlock bd = a.rblk[blockIdx.x];            // uniform: one scalar load
   const int p = bd.prob;
@@ -158,14 +178,14 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) 
   double2 rq_old = make_double2(0.0, 0.0);
   int4 e = make_int4(-1, -1, -1, -1);
   if (active) {
-    rq_old = a.rq[row];
+    rq_old = to_d2(rqv[row]);
     e = a.ell[row];
   }
   const double2 z = make_double2(0.0, 0.0);
-  const double2 v0 = e.x >= 0 ? a.ps[e.x] : z;
-  const double2 v1 = e.y >= 0 ? a.ps[e.y] : z;
-  const double2 v2 = e.z >= 0 ? a.ps[e.z] : z;
-  const double2 v3 = e.w >= 0 ? a.ps[e.w] : z;
+  const double2 v0 = e.x >= 0 ? to_d2(psv[e.x]) : z;
+  const double2 v1 = e.y >= 0 ? to_d2(psv[e.y]) : z;
+  const double2 v2 = e.z >= 0 ? to_d2(psv[e.z]) : z;
+  const double2 v3 = e.w >= 0 ? to_d2(psv[e.w]) : z;
   __syncthreads();
   if (s_done != 0) return;                           // problem converged or stopped
   const int k = base + rel;
@@ -200,18 +220,21 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) 
     if (e.w < -1) {                                  // long row: rest of its run in perm
       const int32_t t1 = a.seg_off[row + 1];
       for (int32_t t = -(e.w + 2); t < t1; ++t) {
-        const double2 v = a.ps[a.perm[t]];
+        const double2 v = to_d2(psv[a.perm[t]]);
         qv += fma(beta, v.x, v.y);
       }
     }
-    a.rq[row] = make_double2(fma(-alpha_prev, rq_old.y, rq_old.x), qv);
+    rqv[row] = make_pair<P>(NR ? 0.0 : fma(-alpha_prev, rq_old.y, rq_old.x), qv);
   }
   const double part = block_sum(qv * qv, sh);
   if (threadIdx.x == 0) a.part_q[blockIdx.x] = part;
 }
 
+template <typename P, bool NR>
 __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) {
   __shared__ double sh[16];
+  const P* const rqv = static_cast<const P*>(a.rq);
+  P* const psv = static_cast<P*>(a.ps);
   __shared__ int s_done;
   const ColBlock bd = a.cblk[blockIdx.x];
   const int p = bd.prob;
@@ -225,13 +248,13 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) 
   double c_old = 0.0;
   double2 g[kPrefetch];
   if (active) {
-    ps_old = a.ps[j];
+    ps_old = to_d2(psv[j]);
     c_old = a.c[j];
   }
 #pragma unroll
   for (int l = 0; l < kPrefetch; ++l) {
     g[l] = make_double2(0.0, 0.0);
-    if (active && l < bd.K) g[l] = a.rq[a.rowmap[bd.rmap_off + l * bd.n + jl]];
+    if (active && l < bd.K) g[l] = to_d2(rqv[a.rowmap[bd.rmap_off + l * bd.n + jl]]);
   }
   __syncthreads();
   if (s_done != 0) return;
@@ -250,17 +273,90 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) 
   if (active) {
     const double pv = fma(beta, ps_old.x, ps_old.y);
     a.c[j] = fma(alpha, pv, c_old);
+    if (NR) {
+      double qs = 0.0;                               // (A^T q)_j
 #pragma unroll
-    for (int l = 0; l < kPrefetch; ++l)
-      if (l < bd.K) sv += fma(-alpha, g[l].y, g[l].x);
-    for (int l = kPrefetch; l < bd.K; ++l) {
-      const double2 v = a.rq[a.rowmap[bd.rmap_off + l * bd.n + jl]];
-      sv += fma(-alpha, v.y, v.x);
+      for (int l = 0; l < kPrefetch; ++l)
+        if (l < bd.K) qs += g[l].y;
+      for (int l = kPrefetch; l < bd.K; ++l)
+        qs += to_d2(rqv[a.rowmap[bd.rmap_off + l * bd.n + jl]]).y;
+      sv = fma(-alpha, qs, ps_old.y);
+    } else {
+#pragma unroll
+      for (int l = 0; l < kPrefetch; ++l)
+        if (l < bd.K) sv += fma(-alpha, g[l].y, g[l].x);
+      for (int l = kPrefetch; l < bd.K; ++l) {
+        const double2 v = to_d2(rqv[a.rowmap[bd.rmap_off + l * bd.n + jl]]);
+        sv += fma(-alpha, v.y, v.x);
+      }
     }
-    a.ps[j] = make_double2(pv, sv);
+    psv[j] = make_pair<P>(pv, sv);
   }
   const double part = block_sum(sv * sv, sh);
   if (threadIdx.x == 0) a.part_s[blockIdx.x] = part;
+}
+
+// ---- mixed precision: FP32 CGLS rounds with FP64 residual refinement ----
+// r64 = b - A c in FP64 (c is FP64), q = 0; resets the round's iteration
+// state; problems already finished keep their stop flag.
+__global__ __launch_bounds__(kBlock) void refine_rows_kernel(CglsArgs a,
+                                                             const double* __restrict__ b) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) a.state[0] = 0;
+  if (g < a.nprob) { a.done[g] = a.outer_done[g]; a.flags[g] = 0; }
+  const RowBlock bd = a.rblk[blockIdx.x];
+  const int32_t row = bd.row0 + threadIdx.x;
+  if (row >= bd.row_end) return;
+  const int4 e = a.ell[row];
+  double acc = 0.0;
+  if (e.x >= 0) acc += a.c[e.x];
+  if (e.y >= 0) acc += a.c[e.y];
+  if (e.z >= 0) acc += a.c[e.z];
+  if (e.w >= 0) acc += a.c[e.w];
+  if (e.w < -1) {
+    const int32_t t1 = a.seg_off[row + 1];
+    for (int32_t t = -(e.w + 2); t < t1; ++t) acc += a.c[a.perm[t]];
+  }
+  const double r = b[row] - acc;
+  a.r64[row] = r;
+  static_cast<float2*>(a.rq)[row] = make_float2((float)r, 0.0f);
+}
+
+// s64 = A^T r64 in FP64; (p, s) = (0, fp32(s64)); partials of ||fp32(s)||^2
+// (the round's CG start) and of ||s64||^2 (the FP64 normal residual).
+__global__ __launch_bounds__(kBlock) void refine_cols_kernel(CglsArgs a) {
+  __shared__ double sh[16];
+  const ColBlock bd = a.cblk[blockIdx.x];
+  const int32_t j = bd.col0 + threadIdx.x;
+  double s64 = 0.0, s32 = 0.0;
+  if (j < bd.col_end) {
+    const int32_t jl = j - bd.col_off;
+    for (int l = 0; l < bd.K; ++l) s64 += a.r64[a.rowmap[bd.rmap_off + l * bd.n + jl]];
+    const float sf = (float)s64;
+    s32 = sf;
+    static_cast<float2*>(a.ps)[j] = make_float2(0.0f, sf);
+  }
+  const double p32 = block_sum(s32 * s32, sh);
+  const double p64 = block_sum(s64 * s64, sh);
+  if (threadIdx.x == 0) { a.part_s[blockIdx.x] = p32; a.part_true[blockIdx.x] = p64; }
+}
+
+// Per problem (one workgroup each): the FP64 normal residual of this round;
+// round 0 records it as the reference, later rounds finish the problem when
+// it has dropped to tol_outer^2 of the reference (or is zero / not finite).
+__global__ __launch_bounds__(kBlock) void refine_check_kernel(CglsArgs a, int round,
+                                                              double tol2_outer) {
+  __shared__ double sh[16];
+  const int p = blockIdx.x;
+  const ProbInfo pi = a.prob[p];
+  const double g = block_sum(load_partials(a.part_true, pi.cblk_off, pi.ncblk), sh);
+  if (threadIdx.x != 0) return;
+  if (a.outer_done[p] != 0) return;
+  if (round == 0) a.gtrue0[p] = g;
+  a.gtrue[p] = g;
+  const double g0 = round == 0 ? g : a.gtrue0[p];
+  const bool fin = !(g > 0.0) || !(g > tol2_outer * g0) || !isfinite(g0);
+  if (fin) { a.outer_done[p] = round + 1; a.done[p] = 1; }
 }
 
 // gamma of the current column partials into ring entry k, for every problem
@@ -279,6 +375,11 @@ __global__ void cgls_set_base_kernel(int32_t* state, int base) {
 
 __global__ void cgls_fill_i32_kernel(int32_t* v, int n, int value) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = value;
+}
+
+__global__ void cgls_fill_f64_kernel(double* v, int64_t n, double value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = value;
 }
 
@@ -316,12 +417,31 @@ hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipSt
 }
 
 hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_rows_kernel, dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, rel);
+  if (a.fp32)
+    hipLaunchKernelGGL((cgls_rows_kernel<float2, true>), dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, rel);
+  else
+    hipLaunchKernelGGL((cgls_rows_kernel<double2, false>), dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, rel);
   return hipGetLastError();
 }
 
 hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_cols_kernel, dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, rel);
+  if (a.fp32)
+    hipLaunchKernelGGL((cgls_cols_kernel<float2, true>), dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, rel);
+  else
+    hipLaunchKernelGGL((cgls_cols_kernel<double2, false>), dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, rel);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(const CglsArgs& a, const double* b, int round, double tol2_outer,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(refine_rows_kernel, dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(refine_cols_kernel, dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(refine_check_kernel, dim3((unsigned)a.nprob), dim3(kBlock), 0, s, a, round,
+                     tol2_outer);
   return hipGetLastError();
 }
 
@@ -344,6 +464,13 @@ hipError_t launch_cgls_set_base(int32_t* state, int base, hipStream_t s) {
 hipError_t launch_fill_i32(int32_t* v, int n, int value, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(cgls_fill_i32_kernel, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s,
+                     v, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* v, int64_t n, double value, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cgls_fill_f64_kernel, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s,
                      v, n, value);
   return hipGetLastError();
 }

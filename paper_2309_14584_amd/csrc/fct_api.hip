@@ -583,6 +583,7 @@ fct_status fct_plan_get_info(const fct_plan* p, fct_plan_info* o) {
   o->total_rows = p->M; o->max_points = p->max_points; o->max_degree = p->maxdeg;
   o->dct_levels = (int32_t)p->fwd.size(); o->device_bytes = p->device_bytes;
   o->problems = p->nprob;
+  for (const auto& pi : p->probs) o->entries += (int64_t)pi.K * pi.n;
   return FCT_OK;
 }
 
@@ -652,6 +653,12 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   FCT_HIP(dalloc(&w->d_rq, p->M, nullptr));
   FCT_HIP(dalloc(&w->d_ps, p->n, nullptr));
   FCT_HIP(dalloc(&w->d_ctmp, p->n, nullptr));
+  FCT_HIP(dalloc(&w->d_r64, p->M, nullptr));
+  FCT_HIP(dalloc(&w->d_part_true, p->ncblk, nullptr));
+  FCT_HIP(dalloc(&w->d_gtrue, 2 * P, nullptr));
+  FCT_HIP(dalloc(&w->d_outer, P, nullptr));
+  FCT_HIP(hipHostMalloc((void**)&w->h_outer, sizeof(int32_t) * P, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_gtrue, sizeof(double) * 2 * P, hipHostMallocDefault));
   FCT_HIP(dalloc(&w->d_part_q, p->nrblk, nullptr));
   FCT_HIP(dalloc(&w->d_part_s, p->ncblk, nullptr));
   FCT_HIP(dalloc(&w->d_ring, 8 * P, nullptr));
@@ -674,13 +681,16 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
 
 void fct_ws_destroy(fct_ws* w) {
   if (!w) return;
-  if (w->graph_exec) (void)hipGraphExecDestroy(w->graph_exec);
+  for (auto& g : w->graph_exec) if (g) (void)hipGraphExecDestroy(g);
   if (w->graph_stream) (void)hipStreamDestroy(w->graph_stream);
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
   dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
   dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_ring); dfree(w->d_gamma0);
   dfree(w->d_done); dfree(w->d_flags); dfree(w->d_done_tmp); dfree(w->d_state);
-  dfree(w->d_state_tmp);
+  dfree(w->d_state_tmp); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
+  dfree(w->d_outer);
+  if (w->h_outer) (void)hipHostFree(w->h_outer);
+  if (w->h_gtrue) (void)hipHostFree(w->h_gtrue);
   if (w->h_done) (void)hipHostFree(w->h_done);
   if (w->h_ring) (void)hipHostFree(w->h_ring);
   if (w->h_gamma0) (void)hipHostFree(w->h_gamma0);
@@ -789,86 +799,67 @@ fct_status fct_apply_AT(const fct_plan* p, const double* d_r, double* d_s, hipSt
   return FCT_OK;
 }
 
-fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
-                     const fct_solve_opts* opts_in, fct_solve_info* info, fct_ws* ws,
-                     hipStream_t s) {
-  if (!p || !d_b || !d_c) { set_error("NULL argument"); return FCT_EINVAL; }
-  if (!dev_ok(p)) return FCT_EINVAL;
-  fct_status st = check_ws(p, ws);
-  if (st != FCT_OK) return st;
-  fct_solve_opts o;
-  std::memset(&o, 0, sizeof(o));
-  if (opts_in) o = *opts_in;
-  if (o.mode != FCT_SOLVE_F64) { set_error("unsupported solve mode %d", o.mode); return FCT_EINVAL; }
-  if (o.maxit <= 0) o.maxit = 4000;
-  if (o.check_every <= 0) o.check_every = 32;
-  if (o.tol <= 0.0) o.tol = 1e-14;
-  if (o.check_every > 4096) o.check_every = 4096;
-  if (o.maxit > (1 << 30)) { set_error("maxit too large"); return FCT_EINVAL; }
+// Graph of `chunk` CGLS iterations for the given arguments (cached per
+// precision in the workspace; rebuilt when the chunk, d_c or tol change).
+static fct_status ensure_graph(fct_ws* ws, const CglsArgs& a, int chunk) {
+  const int g = a.fp32 ? 1 : 0;
+  if (ws->graph_exec[g] && ws->graph_chunk[g] == chunk && ws->graph_c[g] == a.c &&
+      ws->graph_tol2[g] == a.tol2)
+    return FCT_OK;
+  if (ws->graph_exec[g]) { (void)hipGraphExecDestroy(ws->graph_exec[g]); ws->graph_exec[g] = nullptr; }
+  hipGraph_t gr = nullptr;
+  FCT_HIP(hipStreamBeginCapture(ws->graph_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int rel = 0; rel < chunk && e == hipSuccess; ++rel) e = launch_cgls_iter(a, rel, ws->graph_stream);
+  if (e == hipSuccess) e = launch_cgls_advance(a.state, chunk, ws->graph_stream);
+  hipError_t e2 = hipStreamEndCapture(ws->graph_stream, &gr);
+  if (e != hipSuccess) { if (gr) (void)hipGraphDestroy(gr); return hip_fail(e, "graph capture", __FILE__, __LINE__); }
+  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture", __FILE__, __LINE__);
+  e = hipGraphInstantiate(&ws->graph_exec[g], gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) { ws->graph_exec[g] = nullptr; return hip_fail(e, "hipGraphInstantiate", __FILE__, __LINE__); }
+  ws->graph_chunk[g] = chunk; ws->graph_c[g] = a.c; ws->graph_tol2[g] = a.tol2;
+  return FCT_OK;
+}
+
+// CGLS iterations until every problem has stopped or `maxit` iterations ran.
+// Chunks of iterations are kept two deep in the stream: while chunk i runs,
+// the host reads the per-problem convergence state copied after chunk i-1.
+// From each running problem's observed decrease of ||A^T r||^2 the host
+// predicts how many iterations remain and shortens the next chunk
+// accordingly, so few (early-exiting) launches run after the last problem
+// has converged.  Returns the number of iterations enqueued.
+static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, int maxit,
+                            int chunk, bool use_graph, hipStream_t s, int* queued_out) {
   const int P = p->nprob;
-  CglsArgs a;
-  a.rblk = p->d_rblk; a.cblk = p->d_cblk; a.prob = p->d_prob;
-  a.nrblk = p->nrblk; a.ncblk = p->ncblk; a.nprob = P;
-  a.ell = p->d_ell; a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.rowmap = p->d_rowmap;
-  a.rq = ws->d_rq; a.ps = ws->d_ps; a.c = d_c;
-  a.part_q = ws->d_part_q; a.part_s = ws->d_part_s;
-  a.ring = ws->d_ring; a.gamma0 = ws->d_gamma0; a.done = ws->d_done; a.flags = ws->d_flags;
-  a.state = ws->d_state; a.tol2 = o.tol * o.tol;
-
-  FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
-  const int chunk = o.check_every;
-  const bool timing = o.timing != 0;
-  if (o.use_graph) {
-    const bool fresh = ws->graph_exec == nullptr || ws->graph_chunk != chunk ||
-                       ws->graph_c != d_c || ws->graph_tol2 != a.tol2;
-    if (fresh) {
-      if (ws->graph_exec) { (void)hipGraphExecDestroy(ws->graph_exec); ws->graph_exec = nullptr; }
-      hipGraph_t g = nullptr;
-      FCT_HIP(hipStreamBeginCapture(ws->graph_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e = hipSuccess;
-      for (int rel = 0; rel < chunk && e == hipSuccess; ++rel)
-        e = launch_cgls_iter(a, rel, ws->graph_stream);
-      if (e == hipSuccess) e = launch_cgls_advance(ws->d_state, chunk, ws->graph_stream);
-      hipError_t e2 = hipStreamEndCapture(ws->graph_stream, &g);
-      if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(e, "graph capture", __FILE__, __LINE__); }
-      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture", __FILE__, __LINE__);
-      e = hipGraphInstantiate(&ws->graph_exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) { ws->graph_exec = nullptr; return hip_fail(e, "hipGraphInstantiate", __FILE__, __LINE__); }
-      ws->graph_chunk = chunk; ws->graph_c = d_c; ws->graph_tol2 = a.tol2;
-    }
+  const int g = a.fp32 ? 1 : 0;
+  if (use_graph) {
+    fct_status st = ensure_graph(ws, a, chunk);
+    if (st != FCT_OK) return st;
   }
-
-  // Chunks of iterations are kept two deep in the stream: while chunk i
-  // runs, the host reads the per-problem convergence state copied after
-  // chunk i-1.  From each running problem's observed decrease of
-  // ||A^T r||^2 the host predicts how many iterations remain and shortens
-  // the next chunk accordingly, so few (early-exiting) launches run after
-  // the last problem has converged.
   int upto[2] = {0, 0};
   int head = 0, inflight = 0, queued = 0;
-  bool all_done = false;
   std::vector<int> kprev((size_t)P, -1), klast((size_t)P, -1);
   std::vector<double> gprev((size_t)P, 0.0), glast((size_t)P, 0.0);
-  int target = o.maxit;
+  int target = maxit;
   while (true) {
-    while (inflight < 2 && queued < o.maxit && queued < target) {
-      int c = std::min(chunk, std::min(o.maxit, target) - queued);
+    while (inflight < 2 && queued < maxit && queued < target) {
+      int c = std::min(chunk, std::min(maxit, target) - queued);
       if (c < 1) c = 1;
-      if (o.use_graph && c == chunk) {
-        FCT_HIP(hipGraphLaunch(ws->graph_exec, s));
+      if (use_graph && c == chunk) {
+        FCT_HIP(hipGraphLaunch(ws->graph_exec[g], s));
       } else {
         for (int rel = 0; rel < c; ++rel) FCT_HIP(launch_cgls_iter(a, rel, s));
-        FCT_HIP(launch_cgls_advance(ws->d_state, c, s));
+        FCT_HIP(launch_cgls_advance(a.state, c, s));
       }
       queued += c;
       const int sl = (head + inflight) & 1;
       upto[sl] = queued;
-      FCT_HIP(hipMemcpyAsync(ws->h_done + (size_t)sl * P, ws->d_done, sizeof(int32_t) * P,
+      FCT_HIP(hipMemcpyAsync(ws->h_done + (size_t)sl * P, a.done, sizeof(int32_t) * P,
                              hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(ws->h_ring + (size_t)sl * 8 * P, ws->d_ring, sizeof(double) * 8 * P,
+      FCT_HIP(hipMemcpyAsync(ws->h_ring + (size_t)sl * 8 * P, a.ring, sizeof(double) * 8 * P,
                              hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(ws->h_gamma0 + (size_t)sl * P, ws->d_gamma0, sizeof(double) * P,
+      FCT_HIP(hipMemcpyAsync(ws->h_gamma0 + (size_t)sl * P, a.gamma0, sizeof(double) * P,
                              hipMemcpyDeviceToHost, s));
       FCT_HIP(hipEventRecord(ws->ev[sl], s));
       ++inflight;
@@ -882,7 +873,7 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     const double* hr = ws->h_ring + (size_t)sl * 8 * P;
     const double* hg0 = ws->h_gamma0 + (size_t)sl * P;
     const int k = upto[sl] - 1;
-    all_done = true;
+    bool all_done = true;
     int need_max = -1;
     for (int q = 0; q < P; ++q) {
       if (hd[q] != 0) continue;
@@ -895,31 +886,144 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
         const double need = (std::log(a.tol2 * g0) - std::log(glast[q])) / lrate;
         if (std::isfinite(need) && need >= 0.0) {
           const double t = (double)k + need + 2.0;
-          need_max = std::max(need_max, t < (double)o.maxit ? (int)t + 1 : o.maxit);
+          need_max = std::max(need_max, t < (double)maxit ? (int)t + 1 : maxit);
         } else {
-          need_max = o.maxit;
+          need_max = maxit;
         }
       } else {
-        need_max = o.maxit;
+        need_max = maxit;
       }
     }
     if (all_done) break;
     target = std::max(need_max, queued + 1);
   }
   FCT_HIP(hipStreamSynchronize(s));
-  // final per-problem state (slot 2)
+  *queued_out = queued;
+  return FCT_OK;
+}
+
+// Mean kernel times from back-to-back launches bracketed by HIP events on
+// this stream, after the results were read: every problem re-runs
+// iteration k (stop test off, its own stop flags untouched), first the row
+// kernel, then the column kernel with its coefficient update directed into
+// scratch, so d_c keeps the solution.
+static fct_status time_kernels(fct_ws* ws, const CglsArgs& a, int k, int P, hipStream_t s,
+                               double* rows_us, double* cols_us) {
+  constexpr int kReps = 200;
+  CglsArgs t = a;
+  t.tol2 = 0.0;
+  t.c = ws->d_ctmp;
+  t.done = ws->d_done_tmp;
+  t.state = ws->d_state_tmp;
+  FCT_HIP(launch_fill_i32(ws->d_done_tmp, P, 0, s));
+  FCT_HIP(launch_cgls_set_base(ws->d_state_tmp, k, s));
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  struct EG { hipEvent_t* e; ~EG() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } eg{ev};
+  for (auto& e : ev) FCT_HIP(hipEventCreate(&e));
+  FCT_HIP(hipEventRecord(ev[0], s));
+  for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_rows(t, 0, s));
+  FCT_HIP(hipEventRecord(ev[1], s));
+  for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_cols(t, 0, s));
+  FCT_HIP(hipEventRecord(ev[2], s));
+  FCT_HIP(hipEventSynchronize(ev[2]));
+  float m1 = 0.f, m2 = 0.f;
+  FCT_HIP(hipEventElapsedTime(&m1, ev[0], ev[1]));
+  FCT_HIP(hipEventElapsedTime(&m2, ev[1], ev[2]));
+  *rows_us = 1e3 * m1 / kReps;
+  *cols_us = 1e3 * m2 / kReps;
+  return FCT_OK;
+}
+
+fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
+                     const fct_solve_opts* opts_in, fct_solve_info* info, fct_ws* ws,
+                     hipStream_t s) {
+  if (!p || !d_b || !d_c) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  fct_status st = check_ws(p, ws);
+  if (st != FCT_OK) return st;
+  fct_solve_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts_in) o = *opts_in;
+  if (o.mode != FCT_SOLVE_F64 && o.mode != FCT_SOLVE_F32_REFINE && o.mode != FCT_SOLVE_F32) {
+    set_error("unknown solve mode %d", o.mode);
+    return FCT_EINVAL;
+  }
+  const bool mixed = o.mode != FCT_SOLVE_F64;
+  if (o.maxit <= 0) o.maxit = 4000;
+  if (o.check_every <= 0) o.check_every = 32;
+  if (o.tol <= 0.0) o.tol = o.mode == FCT_SOLVE_F32 ? 2e-7 : 1e-14;
+  if (o.check_every > 4096) o.check_every = 4096;
+  if (o.maxit > (1 << 30)) { set_error("maxit too large"); return FCT_EINVAL; }
+  if (o.max_refine <= 0) o.max_refine = 12;
+  if (o.inner_tol <= 0.0) o.inner_tol = 1e-5;
+  const int P = p->nprob;
+  CglsArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.rblk = p->d_rblk; a.cblk = p->d_cblk; a.prob = p->d_prob;
+  a.nrblk = p->nrblk; a.ncblk = p->ncblk; a.nprob = P;
+  a.ell = p->d_ell; a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.rowmap = p->d_rowmap;
+  a.rq = ws->d_rq; a.ps = ws->d_ps; a.c = d_c; a.fp32 = mixed ? 1 : 0;
+  a.part_q = ws->d_part_q; a.part_s = ws->d_part_s;
+  a.ring = ws->d_ring; a.gamma0 = ws->d_gamma0; a.done = ws->d_done; a.flags = ws->d_flags;
+  a.state = ws->d_state;
+  a.r64 = ws->d_r64; a.part_true = ws->d_part_true; a.gtrue0 = ws->d_gtrue;
+  a.gtrue = ws->d_gtrue + P; a.outer_done = ws->d_outer;
+  const int chunk = o.check_every;
+
+  std::vector<int> iters((size_t)P, 0), rounds((size_t)P, 0);
   int32_t* fd = ws->h_done + (size_t)2 * P;
   double* fr = ws->h_ring + (size_t)2 * 8 * P;
   double* fg0 = ws->h_gamma0 + (size_t)2 * P;
-  FCT_HIP(hipMemcpyAsync(fd, ws->d_done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
-  FCT_HIP(hipStreamSynchronize(s));
-  bool any_running = false;
-  for (int q = 0; q < P; ++q) any_running |= fd[q] == 0;
-  if (any_running) FCT_HIP(launch_cgls_gamma(a, queued, s));
-  FCT_HIP(hipMemcpyAsync(fr, ws->d_ring, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, s));
-  FCT_HIP(hipMemcpyAsync(fg0, ws->d_gamma0, sizeof(double) * P, hipMemcpyDeviceToHost, s));
-  FCT_HIP(hipMemcpyAsync(ws->h_flags, ws->d_flags, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
-  FCT_HIP(hipStreamSynchronize(s));
+  int total_queued = 0, last_queued = 0;
+  if (!mixed) {
+    a.tol2 = o.tol * o.tol;
+    FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
+    st = cgls_loop(p, ws, a, o.maxit, chunk, o.use_graph != 0, s, &last_queued);
+    if (st != FCT_OK) return st;
+    total_queued = last_queued;
+    FCT_HIP(hipMemcpyAsync(fd, a.done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipStreamSynchronize(s));
+    bool any_running = false;
+    for (int q = 0; q < P; ++q) any_running |= fd[q] == 0;
+    if (any_running) FCT_HIP(launch_cgls_gamma(a, last_queued, s));
+    FCT_HIP(hipMemcpyAsync(fr, a.ring, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipMemcpyAsync(fg0, a.gamma0, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipMemcpyAsync(ws->h_flags, a.flags, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < P; ++q) iters[(size_t)q] = fd[q] != 0 ? fd[q] - 1 : last_queued;
+  } else {
+    // FP32 CGLS rounds, each started from the FP64 residual of the FP64
+    // iterate; the outer test is the FP64 normal residual.
+    a.tol2 = o.inner_tol * o.inner_tol;
+    const double tol2_outer = o.tol * o.tol;
+    if (!o.warm_start) FCT_HIP(launch_fill_f64(d_c, p->n, 0.0, s));
+    FCT_HIP(launch_fill_i32(ws->d_outer, P, 0, s));
+    const int nround = o.mode == FCT_SOLVE_F32 ? 1 : o.max_refine;
+    int budget = o.maxit;
+    for (int round = 0; round <= nround; ++round) {
+      FCT_HIP(launch_refine(a, d_b, round, tol2_outer, s));
+      FCT_HIP(hipMemcpyAsync(ws->h_outer, ws->d_outer, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipStreamSynchronize(s));
+      bool all = true;
+      for (int q = 0; q < P; ++q) all &= ws->h_outer[q] != 0;
+      if (all || round == nround || budget <= 0) break;
+      if (o.mode == FCT_SOLVE_F32) a.tol2 = o.tol * o.tol;   // one round to the requested tol
+      st = cgls_loop(p, ws, a, budget, chunk, o.use_graph != 0, s, &last_queued);
+      if (st != FCT_OK) return st;
+      total_queued += last_queued;
+      budget -= last_queued;
+      FCT_HIP(hipMemcpyAsync(fd, a.done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < P; ++q) {
+        if (ws->h_outer[q] != 0) continue;
+        iters[(size_t)q] += fd[q] != 0 ? fd[q] - 1 : last_queued;
+        rounds[(size_t)q] = round + 1;
+      }
+    }
+    FCT_HIP(hipMemcpyAsync(ws->h_outer, ws->d_outer, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipMemcpyAsync(ws->h_gtrue, ws->d_gtrue, sizeof(double) * 2 * P, hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipStreamSynchronize(s));
+  }
 
   ws->last.assign((size_t)P, fct_solve_info());
   fct_solve_info agg;
@@ -930,60 +1034,45 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   for (int q = 0; q < P; ++q) {
     fct_solve_info& r = ws->last[(size_t)q];
     std::memset(&r, 0, sizeof(r));
-    const int it = fd[q] != 0 ? fd[q] - 1 : queued;
-    const double g0 = fg0[q], gk = fr[q * 8 + (it & 3)];
+    const int it = iters[(size_t)q];
+    double g0, gk;
+    if (!mixed) {
+      g0 = fg0[q];
+      gk = fr[q * 8 + (it & 3)];
+      r.converged = (fd[q] != 0 && ws->h_flags[q] == 0) ? 1 : 0;
+      if (fd[q] == 1 && g0 == 0.0) r.converged = 1;   // A^T b = 0: c_0 is exact
+    } else {
+      g0 = ws->h_gtrue[q];
+      gk = ws->h_gtrue[P + q];
+      r.converged = (ws->h_outer[q] != 0 && std::isfinite(gk)) ? 1 : 0;
+      if (o.mode == FCT_SOLVE_F32) r.converged = gk <= o.tol * o.tol * g0 ? 1 : 0;
+      r.refinements = rounds[(size_t)q];
+    }
     r.iterations = it;
-    r.converged = (fd[q] != 0 && ws->h_flags[q] == 0) ? 1 : 0;
     r.normal_residual0 = std::sqrt(g0);
     r.rel_normal_residual = g0 > 0 ? std::sqrt(gk / g0) : 0.0;
     r.problems = 1;
     r.problems_converged = r.converged;
-    if (!std::isfinite(g0)) nonfinite = true;
-    // a problem with A^T b = 0 has c = c_0 exact
-    if (fd[q] == 1 && g0 == 0.0) { r.converged = 1; r.problems_converged = 1; }
+    if (!std::isfinite(g0)) { nonfinite = true; r.converged = 0; r.problems_converged = 0; }
     max_iter = std::max(max_iter, it);
     agg.problems_converged += r.converged;
+    agg.refinements = std::max(agg.refinements, r.refinements);
     agg.rel_normal_residual = std::max(agg.rel_normal_residual, r.rel_normal_residual);
     agg.normal_residual0 = std::max(agg.normal_residual0, r.normal_residual0);
   }
   agg.iterations = max_iter;
   agg.converged = agg.problems_converged == P ? 1 : 0;
-
-  if (timing && max_iter > 0) {
-    // Mean kernel times from back-to-back launches bracketed by HIP events
-    // on this stream, after the results were read: every problem re-runs
-    // iteration max_iter-1 (stop test off, its own stop flags untouched),
-    // first the row kernel, then the column kernel with its coefficient
-    // update directed into scratch, so d_c keeps the solution.
-    constexpr int kReps = 200;
-    CglsArgs t = a;
-    t.tol2 = 0.0;
-    t.c = ws->d_ctmp;
-    t.done = ws->d_done_tmp;
-    t.state = ws->d_state_tmp;
-    FCT_HIP(launch_fill_i32(ws->d_done_tmp, P, 0, s));
-    FCT_HIP(launch_cgls_set_base(ws->d_state_tmp, max_iter - 1, s));
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    struct EG { hipEvent_t* e; ~EG() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } eg{ev};
-    for (auto& e : ev) FCT_HIP(hipEventCreate(&e));
-    FCT_HIP(hipEventRecord(ev[0], s));
-    for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_rows(t, 0, s));
-    FCT_HIP(hipEventRecord(ev[1], s));
-    for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_cols(t, 0, s));
-    FCT_HIP(hipEventRecord(ev[2], s));
-    FCT_HIP(hipEventSynchronize(ev[2]));
-    float m1 = 0.f, m2 = 0.f;
-    FCT_HIP(hipEventElapsedTime(&m1, ev[0], ev[1]));
-    FCT_HIP(hipEventElapsedTime(&m2, ev[1], ev[2]));
-    agg.rows_kernel_us = 1e3 * m1 / kReps;
-    agg.cols_kernel_us = 1e3 * m2 / kReps;
+  if (o.timing && last_queued > 0) {
+    st = time_kernels(ws, a, std::max(0, last_queued - 1), P, s, &agg.rows_kernel_us,
+                      &agg.cols_kernel_us);
+    if (st != FCT_OK) return st;
   }
   if (info) *info = agg;
   if (nonfinite) { set_error("||A^T b|| is not finite"); return FCT_ENONFINITE; }
   if (!agg.converged) {
     set_error("CGLS: %d of %d problems did not converge within %d iterations "
-              "(largest relative normal residual %.3e)", P - agg.problems_converged, P, queued,
-              agg.rel_normal_residual);
+              "(largest relative normal residual %.3e)", P - agg.problems_converged, P,
+              total_queued, agg.rel_normal_residual);
     return FCT_ENOCONV;
   }
   return FCT_OK;

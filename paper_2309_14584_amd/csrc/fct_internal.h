@@ -153,8 +153,9 @@ struct CglsArgs {
   const int32_t* seg_off;
   const int32_t* perm;
   const int32_t* rowmap;
-  double2* rq;        // [M] (r, q) per row
-  double2* ps;        // [n] (p, s) per column
+  void* rq;           // [M] (r, q) per row: double2, or float2 when fp32
+  void* ps;           // [n] (p, s) per column: double2, or float2 when fp32
+  int32_t fp32;       // nonzero: FP32 storage of (r, q) and (p, s)
   double* c;          // [n]
   double* part_q;     // [nrblk]
   double* part_s;     // [ncblk]
@@ -164,6 +165,12 @@ struct CglsArgs {
   int32_t* flags;     // [nprob] 1 = breakdown (A p = 0)
   int32_t* state;     // [0] iteration base
   double tol2;
+  // mixed precision (FP32 rounds refined in FP64)
+  double* r64;        // [M] FP64 residual b - A c of the round
+  double* part_true;  // [ncblk] partials of the FP64 normal residual
+  double* gtrue0;     // [nprob] FP64 ||A^T r||^2 of round 0
+  double* gtrue;      // [nprob] FP64 ||A^T r||^2 of the latest round
+  int32_t* outer_done;// [nprob] round+1 at which the problem finished, 0 while refining
 };
 hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipStream_t s);
 hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s);
@@ -174,6 +181,10 @@ hipError_t launch_cgls_advance(int32_t* state, int chunk, hipStream_t s);
 hipError_t launch_cgls_gamma(const CglsArgs& a, int k, hipStream_t s);
 hipError_t launch_cgls_set_base(int32_t* state, int base, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* v, int n, int value, hipStream_t s);
+hipError_t launch_fill_f64(double* v, int64_t n, double value, hipStream_t s);
+// one refinement round's start: r64 = b - A c, (p, s) = (0, A^T r), FP64 test
+hipError_t launch_refine(const CglsArgs& a, const double* b, int round, double tol2_outer,
+                         hipStream_t s);
 int64_t segment_blocks(int64_t L);
 
 // batch construction: dst[i] = src[i] + add (i < count)
@@ -237,6 +248,12 @@ struct fct_ws {
   double2* d_rq = nullptr;         // [M]
   double2* d_ps = nullptr;         // [n]
   double* d_ctmp = nullptr;        // [n] coefficient sink of timing launches
+  double* d_r64 = nullptr;         // [M]
+  double* d_part_true = nullptr;   // [ncblk]
+  double* d_gtrue = nullptr;       // [2][nprob] reference and latest FP64 normal residual
+  int32_t* d_outer = nullptr;      // [nprob]
+  int32_t* h_outer = nullptr;      // pinned [nprob]
+  double* h_gtrue = nullptr;       // pinned [2][nprob]
   double* d_part_q = nullptr;      // [nrblk]
   double* d_part_s = nullptr;      // [ncblk]
   double* d_ring = nullptr;        // [nprob][8]
@@ -252,11 +269,11 @@ struct fct_ws {
   double* h_gamma0 = nullptr;      // [3][nprob]
   int32_t* h_flags = nullptr;      // [nprob]
   hipEvent_t ev[2] = {nullptr, nullptr};
-  hipGraphExec_t graph_exec = nullptr;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // FP64, FP32 iteration chunks
   hipStream_t graph_stream = nullptr;
-  int graph_chunk = 0;
-  double* graph_c = nullptr;
-  double graph_tol2 = -1.0;
+  int graph_chunk[2] = {0, 0};
+  double* graph_c[2] = {nullptr, nullptr};
+  double graph_tol2[2] = {-1.0, -1.0};
   // per-problem results of the last solve
   std::vector<fct_solve_info> last;
 };

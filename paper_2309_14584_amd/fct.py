@@ -30,7 +30,7 @@ FCT_PLAN_ALLOW_RANK_DEFICIENT = 1
 
 FAMILY_PLANTED, FAMILY_EXPCOS, FAMILY_GAUSS, FAMILY_RUNGE, FAMILY_OSC = range(5)
 DCT_F64, DCT_F32, DCT_BF16X3 = 0, 1, 2
-SOLVE_F64 = 0
+SOLVE_F64, SOLVE_F32_REFINE, SOLVE_F32 = 0, 1, 2
 
 _vp = ctypes.c_void_p
 _i32, _i64, _u32, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
@@ -40,20 +40,21 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("D", _i32), ("K", _i32), ("n_support", _i64), ("total_points", _i64),
                 ("total_rows", _i64), ("max_points", _i64), ("max_degree", _i32),
                 ("dct_levels", _i32), ("device_bytes", _i64), ("problems", _i32),
-                ("reserved", _i32)]
+                ("reserved", _i32), ("entries", _i64)]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("mode", _i32), ("maxit", _i32), ("check_every", _i32),
                 ("warm_start", _i32), ("use_graph", _i32), ("timing", _i32),
-                ("tol", _dbl)]
+                ("tol", _dbl), ("max_refine", _i32), ("reserved", _i32), ("inner_tol", _dbl)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32),
                 ("rel_normal_residual", _dbl), ("normal_residual0", _dbl),
                 ("rows_kernel_us", _dbl), ("cols_kernel_us", _dbl),
-                ("problems", _i32), ("problems_converged", _i32)]
+                ("problems", _i32), ("problems_converged", _i32),
+                ("refinements", _i32), ("reserved", _i32)]
 
 
 def _sig(name, res, *args):
@@ -143,6 +144,7 @@ class SolveResult:
     cols_kernel_us: float = 0.0
     problems: int = 1
     problems_converged: int = 0
+    refinements: int = 0
 
 
 class Plan:
@@ -174,6 +176,7 @@ class Plan:
         self.D, self.K, self.n = info.D, info.K, info.n_support
         self.M, self.P = info.total_rows, info.total_points
         self.problems = info.problems
+        self.entries = info.entries
         self._ws = None
 
     @classmethod
@@ -194,7 +197,8 @@ class Plan:
         info = SolveInfo()
         _check(_ws_problem_info(self.ws, q, ctypes.byref(info)))
         return SolveResult(info.iterations, bool(info.converged), info.rel_normal_residual,
-                           info.normal_residual0, FCT_OK, 0.0, 0.0, 1, info.problems_converged)
+                           info.normal_residual0, FCT_OK, 0.0, 0.0, 1, info.problems_converged,
+                           info.refinements)
 
     def close(self):
         if self._ws is not None:
@@ -290,11 +294,12 @@ class Plan:
 
     def solve(self, b, out=None, tol=0.0, maxit=0, check_every=0, warm_start=False,
               use_graph=True, mode=SOLVE_F64, raise_on_noconv=True, timing=False,
-              stream=None):
+              max_refine=0, inner_tol=0.0, stream=None):
         torch = _torch()
         out = self._empty(self.n) if out is None else out
         opts = SolveOpts(mode, int(maxit), int(check_every), 1 if warm_start else 0,
-                         1 if use_graph else 0, 1 if timing else 0, float(tol))
+                         1 if use_graph else 0, 1 if timing else 0, float(tol),
+                         int(max_refine), 0, float(inner_tol))
         info = SolveInfo()
         st = _solve(self._h, _ptr(b, torch.float64, self.M, "b"),
                     _ptr(out, torch.float64, self.n, "out"), ctypes.byref(opts),
@@ -304,4 +309,4 @@ class Plan:
         return out, SolveResult(info.iterations, bool(info.converged),
                                 info.rel_normal_residual, info.normal_residual0, st,
                                 info.rows_kernel_us, info.cols_kernel_us, info.problems,
-                                info.problems_converged)
+                                info.problems_converged, info.refinements)

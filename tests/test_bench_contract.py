@@ -23,6 +23,6 @@ def test_profile_record_parses():
     assert rec["kernel"] == "cgls_rows_kernel" and rec["traffic_bytes_per_launch"] > 0
 
     class P:
-        M, n, K = 55008, 18564, 4
-    # 32 M + 4 (M + 1) + 20 K n + 8 (rb + cb) for the D=6 workload
-    assert b.rows_kernel_bytes(P) == 3467716
+        M, entries = 55008, 4 * 18564
+    # 48 M + 16 E for the D=6 workload
+    assert b.rows_kernel_bytes(P) == 48 * 55008 + 16 * 4 * 18564

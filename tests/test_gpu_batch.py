@@ -138,3 +138,20 @@ def test_batched_workload_256(fct):
         n, rows, coff, roff, poff, pts = batch.problem(i)
         c1, _ = plans[i].solve(_dev(b_host[roff:roff + rows]))
         assert np.array_equal(c[coff:coff + n], _host(c1))
+
+
+def test_batch_mixed_precision_matches_alone(fct):
+    probs = _mixed_batch()
+    plans = [fct.Plan(p.support, p.grids) for p in probs]
+    batch = fct.Plan.batch(plans)
+    coeffs = np.concatenate([p.coeffs for p in probs])
+    b = batch.dct(batch.sample(fct.FAMILY_PLANTED, coeffs=_dev(coeffs)))
+    c_b, info = batch.solve(b, mode=fct.SOLVE_F32_REFINE)
+    c_b = _host(c_b)
+    b_host = _host(b)
+    assert info.converged
+    for i, (pl, pr) in enumerate(zip(plans, probs)):
+        n, rows, coff, roff, poff, pts = batch.problem(i)
+        c1, _ = pl.solve(_dev(b_host[roff:roff + rows]), mode=fct.SOLVE_F32_REFINE)
+        assert np.array_equal(c_b[coff:coff + n], _host(c1))
+        assert O.max_rel_err(c_b[coff:coff + n], pr.coeffs) < 1e-10

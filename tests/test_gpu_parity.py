@@ -241,3 +241,48 @@ def test_dct_reduced_precision(fct, prob, mode):
     full = _host(plan.dct_full(_dev(x), mode=mode))
     assert _rel(full, np.concatenate(ref_full)) < bound
     plan.close()
+
+
+# Mixed precision: FP32 CGLS rounds refined in FP64 reach the FP64 bar
+# (1e-10 max-relative); a single FP32 round (pure FP32 vectors) is held to
+# 1e-5.
+@pytest.mark.parametrize("prob", [W.config1(), W.small_problem(3, 4, 6, 1, 6, 6, W.FAMILY_EXPCOS),
+                                  W.small_problem(12, 5, 5, 0, 5, 12, W.FAMILY_PLANTED)],
+                         ids=["cfg1", "expcos_D4", "planted_D5"])
+def test_solve_mixed_precision_small(fct, prob):
+    c_ref, _, _ = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "qr")
+    plan = fct.Plan(prob.support, prob.grids)
+    coeffs = _dev(prob.coeffs) if prob.coeffs is not None else None
+    b = plan.dct(plan.sample(prob.family, prob.params, coeffs=coeffs))
+    c, info = plan.solve(b, mode=fct.SOLVE_F32_REFINE)
+    err = O.max_rel_err(_host(c), c_ref)
+    print(f"refined: iterations={info.iterations} rounds={info.refinements} err={err:.2e}")
+    assert info.converged and err < 1e-10
+    c32, info32 = plan.solve(b, mode=fct.SOLVE_F32)
+    assert O.max_rel_err(_host(c32), c_ref) < 1e-5
+    plan.close()
+
+
+def test_solve_mixed_precision_config2(fct):
+    import os
+    prob = W.config2()
+    c_ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "cfg2_coeffs_qr.npy"))
+    plan = fct.Plan(prob.support, prob.grids)
+    b = plan.dct(plan.sample(prob.family, prob.params))
+    c, info = plan.solve(b, mode=fct.SOLVE_F32_REFINE)
+    err = O.max_rel_err(_host(c), c_ref)
+    print(f"cfg2 refined: iterations={info.iterations} rounds={info.refinements} err={err:.2e}")
+    assert info.converged and err < 1e-10
+    c32, _ = plan.solve(b, mode=fct.SOLVE_F32)
+    err32 = O.max_rel_err(_host(c32), c_ref)
+    print(f"cfg2 fp32: err={err32:.2e}")
+    assert err32 < 1e-5
+    # FP32 and split-BF16x3 transforms feed the FP64 solve: error floors of
+    # the right-hand side (refinement cannot repair b)
+    for mode, bound in [(fct.DCT_F32, 1e-5), (fct.DCT_BF16X3, 1e-3)]:
+        bm = plan.dct(plan.sample(prob.family, prob.params), mode=mode)
+        cm, _ = plan.solve(bm)
+        e = O.max_rel_err(_host(cm), c_ref)
+        print(f"cfg2 dct mode {mode}: err={e:.2e}")
+        assert e < bound
+    plan.close()
