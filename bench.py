@@ -47,17 +47,16 @@ def cpu_baseline(prob, c_gold):
 
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
-PROFILE = os.path.join(ROOT, "profiles", "cgls_cfg2_D6_d12.md")
 CGLS_SRC = os.path.join(ROOT, "paper_2309_14584_amd", "csrc", "cgls_kernels.hip")
 
 
-def measured_traffic():
-    """HBM bytes per row-kernel launch from the committed rocprofv3 counter
+def measured_traffic(profile="cgls_cfg2_D6_d12.md"):
+    """HBM bytes per row-kernel launch from a committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration),
     or None when the kernel source has changed since the counters were taken."""
     import hashlib
     try:
-        text = open(PROFILE).read()
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
         sha = hashlib.sha256(open(CGLS_SRC, "rb").read()).hexdigest()
     except (OSError, IndexError, ValueError):
@@ -82,7 +81,7 @@ def roofline_rows(plan, us):
             "traffic": measured_traffic(), "algorithmic_bytes": algo, "kernel_us": us}
 
 
-def bench_batched(fct, torch, steps):
+def bench_batched(fct, torch, steps, modes=("f64", "f32_refined")):
     """The 256-problem batched workload (D 3..8, total degree 6..16 capped at
     50k coefficients, Alg.-1 grids with the oracle-selected counts, planted
     polynomials): one step = DCT of every grid + one solve of all problems,
@@ -109,6 +108,8 @@ def bench_batched(fct, torch, steps):
            "n_support": batch.n, "total_points": batch.P, "rows": batch.M,
            "plan_seconds": t_plan}
     for name, mode in [("f64", fct.SOLVE_F64), ("f32_refined", fct.SOLVE_F32_REFINE)]:
+        if name not in modes:
+            continue
         def step():
             batch.dct(samples, out=b)
             return batch.solve(b, out=c, mode=mode, raise_on_noconv=False)[1]
@@ -136,10 +137,115 @@ def bench_batched(fct, torch, steps):
             ach = algo / (tinfo.rows_kernel_us * 1e-6) / 1e9
             entry["roofline"] = {"bound": "hbm", "kernel": "cgls_rows_kernel", "achieved": ach,
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                 "traffic": measured_traffic("cgls_batched256.md"),
                                  "algorithmic_bytes": algo}
         res[name] = entry
     batch.close()
     return res
+
+
+def bench_precision(fct, torch, steps):
+    """The precision sweep: D=12, |n|_1 <= 10 (646,646 coefficients), Gaussian
+    bump on the workload's Alg.-1 grids (count from the oracle's Alg.-2 run).
+    For each DCT mode (FP64, FP32, split-BF16x3 on the matrix cores) the DCT
+    is timed alone, then DCT + solve for the FP64 solve and for the
+    mixed-precision solve; errors are max-relative against the oracle's
+    least-squares minimiser.  One step = sample -> DCT -> solve."""
+    import workloads as W
+    gold = os.path.join(ROOT, "tests", "golden")
+    with open(os.path.join(gold, "cfg4_meta.json")) as fh:
+        meta = json.load(fh)
+    c_ref = np.load(os.path.join(gold, "cfg4_coeffs_lsqr.npy"))
+    prob = W.config4(min_grids=meta["K"])
+    t0 = time.perf_counter()
+    plan = fct.Plan(prob.support, prob.grids)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    samples = torch.empty(plan.P, dtype=torch.float64, device=dev)
+    b = torch.empty(plan.M, dtype=torch.float64, device=dev)
+    c = torch.empty(plan.n, dtype=torch.float64, device=dev)
+    res = {"workload": prob.name, "n_support": plan.n, "grids": plan.K,
+           "total_points": plan.P, "rows": plan.M, "plan_seconds": t_plan}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    t_s, _ = timed(lambda: plan.sample(prob.family, prob.params, out=samples), steps)
+    res["sample_ms"] = 1e3 * t_s
+    for dname, dmode in [("dct_f64", fct.DCT_F64), ("dct_f32", fct.DCT_F32),
+                         ("dct_bf16x3", fct.DCT_BF16X3)]:
+        t_d, _ = timed(lambda: plan.dct(samples, out=b, mode=dmode), steps)
+        ent = {"dct_ms": 1e3 * t_d,
+               "dct_grid_samples_per_s": plan.P / t_d}
+        for sname, smode in [("f64", fct.SOLVE_F64), ("f32_refined", fct.SOLVE_F32_REFINE)]:
+            def step():
+                plan.sample(prob.family, prob.params, out=samples)
+                plan.dct(samples, out=b, mode=dmode)
+                return plan.solve(b, out=c, mode=smode, raise_on_noconv=False)[1]
+            dt, info = timed(step, steps)
+            err = float(np.max(np.abs(c.cpu().numpy() - c_ref)) / np.max(np.abs(c_ref)))
+            ent[sname] = {"ms_per_step": 1e3 * dt, "max_rel_err": err,
+                          "recovered_coeffs_per_s": plan.n / dt if err <= TOL else 0.0,
+                          "grid_samples_per_s": plan.P / dt if err <= TOL else 0.0,
+                          "iterations": info.iterations, "refinements": info.refinements}
+        res[dname] = ent
+    plan.dct(samples, out=b)
+    tinfo = plan.solve(b, out=c, timing=True)[1]
+    algo = rows_kernel_bytes(plan)
+    ach = algo / (tinfo.rows_kernel_us * 1e-6) / 1e9
+    res["roofline"] = {"bound": "hbm", "kernel": "cgls_rows_kernel", "achieved": ach,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                       "traffic": measured_traffic("cgls_cfg4_D12_d10.md"),
+                       "algorithmic_bytes": algo, "kernel_us": tinfo.rows_kernel_us,
+                       "cols_kernel_us": tinfo.cols_kernel_us}
+    plan.close()
+    return res
+
+
+def bench_serving(fct, torch, duration, rate=200.0, slots=4):
+    """The serving workload: requests drawn (seeded) from a pool of 64 jobs
+    of four kinds (D2 |n|_1<=16; D6 |n|_1<=12 exp-cos; a batched-workload
+    problem; D20 |n|_1<=4) arrive as a Poisson stream at `rate` per second
+    and are served on `slots` HIP streams with admission under a device-byte
+    budget.  Each job is first run alone once (this also builds and caches
+    its plan); in the timed run every result must equal its alone result bit
+    for bit.  Latency = completion minus arrival."""
+    import workloads as W
+    from paper_2309_14584_amd.serve import Engine, GpuExecutor, Job, latency_summary
+    with open(os.path.join(ROOT, "tests", "golden", "serving_extra_grids.json")) as fh:
+        fx = json.load(fh)
+    pool = W.serving_pool(fx["seed"], extra_grids=fx["extra_grids"])
+    ex = GpuExecutor(fct, torch)
+    t0 = time.perf_counter()
+    alone = {}
+    for j, p in enumerate(pool):
+        alone[j] = ex.run(Job(j, p, 0.0), 0)[0]
+    t_alone = time.perf_counter() - t0
+    arr = W.poisson_arrivals(5, rate, duration)
+    pick = np.random.default_rng(6).integers(0, len(pool), size=len(arr))
+    jobs = [Job(i, pool[int(k)], float(t)) for i, (k, t) in enumerate(zip(pick, arr))]
+    eng = Engine(ex, slots=slots, budget_bytes=128 << 30)
+    t0 = time.perf_counter()
+    res = eng.run(jobs)
+    wall = time.perf_counter() - t0
+    same = sum(np.array_equal(r.c, alone[int(pick[r.id])]) for r in res)
+    coeffs = sum(pool[int(pick[r.id])].n for r in res)
+    lat = latency_summary(res)
+    ex.close()
+    return {"workload": f"{len(pool)}-job pool (cfg1/cfg2/cfg3-style/D20 shapes), "
+                        f"Poisson {rate:g}/s for {duration:g} s, {slots} streams",
+            "requests": len(jobs), "completed": len(res), "identical_to_alone": int(same),
+            "wall_s": wall, "jobs_per_s": len(res) / wall, "coeffs_per_s": coeffs / wall,
+            "p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"],
+            "max_running": eng.stats.max_running, "max_queue": eng.stats.max_queue,
+            "alone_pass_s": t_alone}
 
 
 def main():
@@ -152,6 +258,13 @@ def main():
     ap.add_argument("--skip-batched", action="store_true",
                     help="only the single-problem workload")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--batched-modes", default="f64,f32_refined")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--skip-precision", action="store_true")
+    ap.add_argument("--precision-steps", type=int, default=3)
+    ap.add_argument("--only", choices=["batched", "serving", "precision"],
+                    help="run one sub-workload alone and print its JSON (for profiling)")
+    ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy five times (counter calibration)")
     args = ap.parse_args()
@@ -173,6 +286,17 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 8, "launches": 5}))
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched": bench_batched(fct, torch, args.batched_steps,
+                                                  args.batched_modes.split(","))}), flush=True)
+        return
+    if args.only == "precision":
+        print(json.dumps({"precision_sweep": bench_precision(fct, torch, args.precision_steps)}),
+              flush=True)
+        return
+    if args.only == "serving":
+        print(json.dumps({"serving": bench_serving(fct, torch, args.serving_seconds)}), flush=True)
         return
     prob = W.config2()
     c_gold = np.load(os.path.join(ROOT, "tests", "golden", "cfg2_coeffs_qr.npy"))
@@ -236,7 +360,19 @@ def main():
     out["roofline"]["cols_kernel_us"] = tinfo.cols_kernel_us
     plan.close()
     if not args.skip_batched:
-        out["batched"] = bench_batched(fct, torch, args.batched_steps)
+        out["batched"] = bench_batched(fct, torch, args.batched_steps,
+                                       args.batched_modes.split(","))
+    gold = os.path.join(ROOT, "tests", "golden")
+    if not args.skip_precision:
+        if os.path.exists(os.path.join(gold, "cfg4_meta.json")):
+            out["precision_sweep"] = bench_precision(fct, torch, args.precision_steps)
+        else:
+            out["precision_sweep"] = {"skipped": "oracle reference tests/golden/cfg4_* missing"}
+    if not args.skip_serving:
+        if os.path.exists(os.path.join(gold, "serving_extra_grids.json")):
+            out["serving"] = bench_serving(fct, torch, args.serving_seconds)
+        else:
+            out["serving"] = {"skipped": "tests/golden/serving_extra_grids.json missing"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, c_gold)
     print(json.dumps(out), flush=True)

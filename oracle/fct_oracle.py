@@ -300,11 +300,16 @@ def gram_matrix(plan: Plan) -> np.ndarray:
 # Sampling (Alg. 3, sample f on the L-grid)
 # ---------------------------------------------------------------------------
 
-def grid_coordinates(grid):
-    """Node coordinates of every point of one grid, [P, D], row-major."""
+def grid_coordinates(grid, start: int = 0, stop: int | None = None):
+    """Node coordinates of the points start..stop-1 (flat row-major index)
+    of one grid, [stop - start, D]; by default every point."""
     axes = [lobatto_nodes(int(N)) for N in grid]
-    mesh = np.meshgrid(*axes, indexing="ij")
-    return np.stack([m.reshape(-1) for m in mesh], axis=1)
+    shape = tuple(int(N) + 1 for N in grid)
+    if start == 0 and stop is None:
+        mesh = np.meshgrid(*axes, indexing="ij")
+        return np.stack([m.reshape(-1) for m in mesh], axis=1)
+    idx = np.unravel_index(np.arange(start, stop, dtype=np.int64), shape)
+    return np.stack([axes[i][idx[i]] for i in range(len(shape))], axis=1)
 
 
 def sample_planted(support, coeffs, grid) -> np.ndarray:
@@ -330,7 +335,7 @@ def sample_planted(support, coeffs, grid) -> np.ndarray:
     return out.reshape(-1)
 
 
-def sample_function(family: int, params, grid) -> np.ndarray:
+def sample_function(family: int, params, grid, chunk: int = 1 << 22) -> np.ndarray:
     """Samples of an analytic test function on one grid, FP64, pointwise.
 
     family 1: exp(-sum a_i x_i^2) cos(sum w_i x_i), params = [a_1..a_D, w_1..w_D]
@@ -338,7 +343,17 @@ def sample_function(family: int, params, grid) -> np.ndarray:
     family 3: 1 / (1 + alpha |x|^2)   (f1, Sec. 4.3.1), params = [alpha]
     family 4: sin(3 cos(3 exp|x|^2)) + exp(sin(3 sum x))  (f2, Sec. 4.3.2)
     """
-    X = grid_coordinates(grid)
+    P = int(np.prod([int(N) + 1 for N in grid]))
+    if P > chunk:                      # large grids: the same pointwise formula in slabs
+        out = np.empty(P)
+        for a in range(0, P, chunk):
+            b = min(P, a + chunk)
+            out[a:b] = _function_at(family, params, grid_coordinates(grid, a, b))
+        return out
+    return _function_at(family, params, grid_coordinates(grid))
+
+
+def _function_at(family: int, params, X) -> np.ndarray:
     D = X.shape[1]
     p = np.asarray(params, dtype=np.float64)
     if family == 1:

@@ -153,6 +153,18 @@ __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int 
 // are known; further grids continue in a loop.
 constexpr int kPrefetch = 4;
 
+// In a batch, whether problem p still iterates, read before any operand is
+// loaded so that the workgroups of finished problems cost no memory traffic.
+// The value only gates those loads: the decision to return is taken from the
+// workgroup's LDS copy of the flag after the first barrier.  A wave that
+// sees the flag set during this launch (by the problem's first workgroup)
+// belongs to a workgroup that reaches the same stop decision from the same
+// scalars before it would use any skipped operand.  A single problem never
+// pays for the extra dependent load.
+__device__ __forceinline__ bool live_problem(const CglsArgs& a, int p) {
+  return a.nprob == 1 || __builtin_amdgcn_readfirstlane(a.done[p]) == 0;
+}
+
 // NR: the normal-equation form used by the mixed-precision rounds.  The
 // residual r is not carried; the column kernel updates s = A^T r by
 // s <- s - alpha A^T q, so a round can start from s = A^T (b - A c)
@@ -172,9 +184,10 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) 
   if (threadIdx.x == 0) s_done = a.done[p];
   const int base = a.state[0];
   const double gpart = load_partials(a.part_s, bd.cblk_off, bd.ncblk);
-  // operands that do not depend on this iteration's scalars
+  // operands that do not depend on this iteration's scalars; in a batch a
+  // problem that has stopped issues none of them
   const int32_t row = bd.row0 + threadIdx.x;
-  const bool active = row < bd.row_end;
+  const bool active = row < bd.row_end && live_problem(a, p);
   double2 rq_old = make_double2(0.0, 0.0);
   int4 e = make_int4(-1, -1, -1, -1);
   if (active) {
@@ -242,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) 
   const int base = a.state[0];
   const double dpart = load_partials(a.part_q, bd.rblk_off, bd.nrblk);
   const int32_t j = bd.col0 + threadIdx.x;
-  const bool active = j < bd.col_end;
+  const bool active = j < bd.col_end && live_problem(a, p);
   const int32_t jl = j - bd.col_off;
   double2 ps_old = make_double2(0.0, 0.0);
   double c_old = 0.0;

@@ -147,6 +147,34 @@ class SolveResult:
     refinements: int = 0
 
 
+class Workspace:
+    """A workspace of its own for a plan (fct_ws_create): DCT scratch and
+    solver state.  Calls on one plan that run at the same time, on different
+    streams, each need one of these."""
+
+    def __init__(self, plan):
+        w = _vp()
+        _check(_ws_create(plan._h, ctypes.byref(w)))
+        self._w = w
+
+    @property
+    def handle(self):
+        if self._w is None:
+            raise ValueError("workspace is closed")
+        return self._w
+
+    def close(self):
+        if getattr(self, "_w", None):
+            _ws_destroy(self._w)
+            self._w = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """Alias structure of a support on K Lobatto grids (fct_plan_create)."""
 
@@ -193,9 +221,15 @@ class Plan:
         _check(_plan_problem(self._h, q, *[ctypes.byref(v) for v in vals]))
         return tuple(v.value for v in vals)
 
-    def problem_result(self, q):
+    def new_workspace(self):
+        return Workspace(self)
+
+    def _wsh(self, ws):
+        return self.ws if ws is None else ws.handle
+
+    def problem_result(self, q, ws=None):
         info = SolveInfo()
-        _check(_ws_problem_info(self.ws, q, ctypes.byref(info)))
+        _check(_ws_problem_info(self._wsh(ws), q, ctypes.byref(info)))
         return SolveResult(info.iterations, bool(info.converged), info.rel_normal_residual,
                            info.normal_residual0, FCT_OK, 0.0, 0.0, 1, info.problems_converged,
                            info.refinements)
@@ -253,28 +287,29 @@ class Plan:
         return torch.empty(max(int(n), 1), dtype=torch.float64,
                            device=torch.device("cuda", torch.cuda.current_device()))[: int(n)]
 
-    def sample(self, family, params=(), coeffs=None, out=None, stream=None):
+    def sample(self, family, params=(), coeffs=None, out=None, stream=None, ws=None):
         torch = _torch()
         out = self._empty(self.P) if out is None else out
         prm = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
         cptr = _ptr(coeffs, torch.float64, self.n, "coeffs")
         _check(_sample(self._h, int(family), prm.ctypes.data_as(_vp) if prm.size else None,
                        int(prm.size), cptr, _ptr(out, torch.float64, self.P, "out"),
-                       self.ws if family == FAMILY_PLANTED else None, _stream(stream)))
+                       self._wsh(ws) if family == FAMILY_PLANTED else None, _stream(stream)))
         return out
 
-    def dct(self, samples, out=None, mode=DCT_F64, stream=None):
+    def dct(self, samples, out=None, mode=DCT_F64, stream=None, ws=None):
         torch = _torch()
         out = self._empty(self.M) if out is None else out
         _check(_dct(self._h, _ptr(samples, torch.float64, self.P, "samples"),
-                    _ptr(out, torch.float64, self.M, "out"), mode, self.ws, _stream(stream)))
+                    _ptr(out, torch.float64, self.M, "out"), mode, self._wsh(ws),
+                    _stream(stream)))
         return out
 
-    def dct_full(self, samples, out=None, mode=DCT_F64, stream=None):  # noqa: D401
+    def dct_full(self, samples, out=None, mode=DCT_F64, stream=None, ws=None):
         torch = _torch()
         out = self._empty(self.P) if out is None else out
         _check(_dct_full(self._h, _ptr(samples, torch.float64, self.P, "samples"),
-                         _ptr(out, torch.float64, self.P, "out"), mode, self.ws,
+                         _ptr(out, torch.float64, self.P, "out"), mode, self._wsh(ws),
                          _stream(stream)))
         return out
 
@@ -294,7 +329,7 @@ class Plan:
 
     def solve(self, b, out=None, tol=0.0, maxit=0, check_every=0, warm_start=False,
               use_graph=True, mode=SOLVE_F64, raise_on_noconv=True, timing=False,
-              max_refine=0, inner_tol=0.0, stream=None):
+              max_refine=0, inner_tol=0.0, stream=None, ws=None):
         torch = _torch()
         out = self._empty(self.n) if out is None else out
         opts = SolveOpts(mode, int(maxit), int(check_every), 1 if warm_start else 0,
@@ -303,7 +338,7 @@ class Plan:
         info = SolveInfo()
         st = _solve(self._h, _ptr(b, torch.float64, self.M, "b"),
                     _ptr(out, torch.float64, self.n, "out"), ctypes.byref(opts),
-                    ctypes.byref(info), self.ws, _stream(stream))
+                    ctypes.byref(info), self._wsh(ws), _stream(stream))
         if st != FCT_OK and (raise_on_noconv or st != FCT_ENOCONV):
             _check(st)
         return out, SolveResult(info.iterations, bool(info.converged),

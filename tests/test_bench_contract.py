@@ -18,9 +18,12 @@ def test_profile_record_parses():
     spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
     b = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(b)
-    text = open(b.PROFILE).read()
-    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    assert rec["kernel"] == "cgls_rows_kernel" and rec["traffic_bytes_per_launch"] > 0
+    for name in ("cgls_cfg2_D6_d12.md", "cgls_batched256.md"):
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        assert rec["kernel"].startswith("cgls_rows_kernel<double2")
+        assert rec["traffic_bytes_per_launch"] > 0
+        assert len(rec["cgls_kernels_sha256"]) == 64
 
     class P:
         M, entries = 55008, 4 * 18564

@@ -33,8 +33,8 @@ __all__ = [
     "total_degree_support", "euclidean_degree_support", "grid_points",
     "draw_grids_uniform", "draw_grid_capped", "planted_coefficients",
     "Problem", "config1", "config2", "config3", "config3_problem", "small_problem", "streams",
-    "FAMILY_PLANTED", "FAMILY_EXPCOS", "FAMILY_GAUSS", "FAMILY_RUNGE",
-    "FAMILY_OSC",
+    "config4", "CFG4_MIN_GRIDS", "FAMILY_PLANTED", "FAMILY_EXPCOS", "FAMILY_GAUSS", "FAMILY_RUNGE",
+    "FAMILY_OSC", "SERVING_TYPES", "serving_problem", "serving_pool", "poisson_arrivals",
 ]
 
 # Function-family identifiers (same integers as the C ABI's fct_family).
@@ -213,6 +213,26 @@ def config2(seed: int = 1, min_grids: int = CFG2_MIN_GRIDS) -> Problem:
                    np.concatenate([a, w]), None, seed)
 
 
+CFG4_MIN_GRIDS = 17
+
+
+def config4(seed: int = 3, min_grids: int = CFG4_MIN_GRIDS, d: int = 10) -> Problem:
+    """The precision-sweep workload: D=12, |n|_1 <= d (646,646 coefficients at
+    d = 10), grids with N_i ~ U{2..6} i.i.d. appended until the stacked points
+    reach 3x the support size and the grid floor, f = exp(-|x - x0|^2 /
+    (2 0.8^2)) with x0 ~ U(-0.5, 0.5)^12.  A single such grid already holds
+    ~10^8 points, far beyond 3x; the floor is the grid count at which the
+    oracle finds the stacked system full rank (every dimension's degrees
+    0..d separated by the folds, and exact recovery).  ``d`` < 10 gives a
+    small twin drawn by the same rule."""
+    g_grid, g_par, _ = streams(seed)
+    S = total_degree_support(12, d)
+    grids = draw_grids_uniform(g_grid, 12, 2, 6, len(S), 3.0, min_grids)
+    x0 = g_par.uniform(-0.5, 0.5, size=12)
+    return Problem(f"cfg4_D12_d{d}_gauss", S, grids, FAMILY_GAUSS,
+                   np.concatenate([[0.8], x0]), None, seed)
+
+
 def small_problem(seed: int, D: int, d: int, lo: int, hi: int, K: int,
                   family: int = FAMILY_PLANTED) -> Problem:
     """A small total-degree problem with K i.i.d. U{lo..hi} grids."""
@@ -276,3 +296,92 @@ def config3(seed: int = 2, count: int = 256, extra_grids=None):
                 for _ in range(int(extra_grids[str(i)] if str(i) in extra_grids else extra_grids[i]))]
         p.grids = np.ascontiguousarray(np.concatenate([p.grids, np.array(more, dtype=np.int32)]))
     return out
+
+
+SERVING_TYPES = ("cfg1_shape", "cfg2_shape", "cfg3_style", "D20_d4")
+
+
+def serving_problem(kind: str, rng_grid, rng_coef) -> Problem:
+    """One request of the serving mix.
+
+    cfg1_shape: D=2, |n|_1<=16, K=4 grids N_i ~ U{9..24}, planted polynomial.
+    cfg2_shape: D=6, |n|_1<=12, grids N_i ~ U{4..8} until 2|S| points and
+                K >= 4, exp-cos with a_i ~ U(0.2,1), w_i ~ U(0.5,2).
+    cfg3_style: one problem drawn like the batched workload.
+    D20_d4:     D=20, |n|_1<=4 (10,626 coefficients), Alg.-1 grids (degrees
+                U{1..4}, capped at 4|S| points, single nodes beyond the cap),
+                6D grids to start with, planted.
+    """
+    if kind == "cfg1_shape":
+        S = total_degree_support(2, 16)
+        grids = np.ascontiguousarray(rng_grid.integers(9, 25, size=(4, 2)).astype(np.int32))
+        return Problem(kind, S, grids, FAMILY_PLANTED, np.zeros(0),
+                       planted_coefficients(rng_coef, S))
+    if kind == "cfg2_shape":
+        S = total_degree_support(6, 12)
+        grids = draw_grids_uniform(rng_grid, 6, 4, 8, len(S), 2.0, 4)
+        params = np.concatenate([rng_coef.uniform(0.2, 1.0, size=6),
+                                 rng_coef.uniform(0.5, 2.0, size=6)])
+        return Problem(kind, S, grids, FAMILY_EXPCOS, params, None)
+    if kind == "cfg3_style":
+        p = config3_problem(rng_grid, rng_coef)
+        p.name = kind
+        return p
+    if kind == "D20_d4":
+        S = total_degree_support(20, 4)
+        grids = np.array([draw_grid_capped(rng_grid, 20, 1, 4, 4 * len(S), 0)
+                          for _ in range(6 * 20)], dtype=np.int32)
+        return Problem(kind, S, grids, FAMILY_PLANTED, np.zeros(0),
+                       planted_coefficients(rng_coef, S))
+    raise ValueError(kind)
+
+
+def serving_extra_grid(p: Problem, rng):
+    """One more grid for a serving job, drawn by the job's own rule."""
+    d = int(p.support.max())
+    kind = p.name.rsplit("_", 1)[0]
+    if kind == "cfg1_shape":
+        return rng.integers(9, 25, size=2)
+    if kind == "cfg2_shape":
+        return rng.integers(4, 9, size=6)
+    if kind == "D20_d4":
+        return draw_grid_capped(rng, p.D, 1, d, 4 * p.n, 0)
+    return draw_grid_capped(rng, p.D, 1, d, p.n, 1)
+
+
+def serving_pool(seed: int = 4, per_type: int = 16, extra_grids=None):
+    """The serving workload's pool of seeded jobs: per_type jobs of each of
+    the four kinds, interleaved (job i has kind SERVING_TYPES[i % 4]).
+
+    ``extra_grids`` maps a job index to a number of further grids appended
+    to it, drawn by the job's own rule from a stream of its own (job i:
+    default_rng([seed, 1000 + i])): the oracle's Alg.-2 selection stored
+    under tests/golden/."""
+    g_grid, g_coef, _ = streams(seed)
+    jobs = []
+    for i in range(per_type * len(SERVING_TYPES)):
+        kind = SERVING_TYPES[i % len(SERVING_TYPES)]
+        p = serving_problem(kind, g_grid, g_coef)
+        p.name = f"{kind}_{i}"
+        p.seed = seed
+        jobs.append(p)
+    for key, cnt in (extra_grids or {}).items():
+        i = int(key)
+        p = jobs[i]
+        rng = np.random.default_rng([seed, 1000 + i])
+        more = [serving_extra_grid(p, rng) for _ in range(int(cnt))]
+        if more:
+            p.grids = np.ascontiguousarray(
+                np.concatenate([p.grids, np.array(more, dtype=np.int32)]))
+    return jobs
+
+
+def poisson_arrivals(seed: int, rate: float, duration: float):
+    """Arrival times (seconds) of a Poisson stream with the given rate."""
+    _, _, g_arr = streams(seed)
+    t, out = 0.0, []
+    while True:
+        t += g_arr.exponential(1.0 / rate)
+        if t >= duration:
+            return np.array(out)
+        out.append(t)
