@@ -93,8 +93,10 @@ typedef enum fct_solve_mode {
                                with FP32 vectors (q, p, s) and FP64 inner products,
                                each started from s = A^T (b - A c) computed in FP64
                                for the FP64 iterate c (iterative refinement, which
-                               converges for inconsistent systems too); stops on the
-                               FP64 normal residual */
+                               converges for inconsistent systems too), continuing the
+                               previous round's search direction unless
+                               restart_rounds is set; stops on the FP64 normal
+                               residual */
   FCT_SOLVE_F32 = 2         /* a single such round, to tol (default 2e-7) */
 } fct_solve_mode;
 
@@ -132,7 +134,10 @@ typedef struct fct_solve_opts {
   double tol;           /* stop when ||A^T r||_2 <= tol ||A^T r_0||_2; 0 selects 1e-14
                            (2e-7 for FCT_SOLVE_F32) */
   int32_t max_refine;   /* FCT_SOLVE_F32_REFINE: most rounds; 0 selects 12 */
-  int32_t reserved;
+  int32_t restart_rounds; /* FCT_SOLVE_F32_REFINE: nonzero restarts conjugate gradients
+                           (p = 0) at every round; 0 (default) continues each problem's
+                           last search direction with the recomputed FP64 residual
+                           (a reliable update) */
   double inner_tol;     /* FCT_SOLVE_F32_REFINE: per-round reduction of the FP32
                            normal residual; 0 selects 1e-5 */
 } fct_solve_opts;

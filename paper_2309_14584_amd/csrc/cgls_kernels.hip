@@ -63,9 +63,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// This thread's share of a problem's per-workgroup partials.
+// This thread's share of a problem's per-workgroup partials.  With at most
+// one partial per thread (the usual case) it is a single unconditional load
+// from a clamped index, which the compiler can issue next to the kernel's
+// other independent loads instead of waiting for it in a loop.
 __device__ __forceinline__ double load_partials(const double* __restrict__ part, int32_t off,
                                                 int32_t np) {
+  if (np <= (int32_t)blockDim.x) {
+    const int32_t i = (int32_t)threadIdx.x < np ? (int32_t)threadIdx.x : np - 1;
+    const double v = part[off + i];
+    return (int32_t)threadIdx.x < np ? v : 0.0;
+  }
   double v = 0.0;
   for (int32_t i = threadIdx.x; i < np; i += blockDim.x) v += part[off + i];
   return v;
@@ -81,6 +89,20 @@ __device__ __forceinline__ double ring_alpha(const double* ring, int p, int k) {
 // (x, y) pairs stored in FP64 (double2) or FP32 (float2); arithmetic in FP64.
 __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+// A pair as loaded: double2, or a float2 held as one 64-bit word.  Loads
+// that are merged with a default value (masked lanes) keep the raw word in
+// registers until it is used; a float2 merged as two floats would make the
+// compiler wait for each load before the next one is issued.
+template <typename P> struct RawOf { typedef P type; };
+template <> struct RawOf<float2> { typedef unsigned long long type; };
+__device__ __forceinline__ double2 raw_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 raw_d2(unsigned long long v) {
+  float2 f;
+  __builtin_memcpy(&f, &v, sizeof(f));
+  return make_double2(f.x, f.y);
+}
+template <typename R> __device__ __forceinline__ R raw_zero() { return R{}; }
+
 template <typename P> __device__ __forceinline__ P make_pair(double x, double y);
 template <> __device__ __forceinline__ double2 make_pair<double2>(double x, double y) {
   return make_double2(x, y);
@@ -119,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void cgls_init_rows_kernel(CglsArgs a,
                                                                 const double* __restrict__ b,
                                                                 int warm) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g == 0) a.state[0] = 0;
+  if (g == 0) { a.state[0] = 0; a.state[1] = 0; }
   if (g < a.nprob) { a.done[g] = 0; a.flags[g] = 0; }
   const RowBlock bd = a.rblk[blockIdx.x];
   const int32_t row = bd.row0 + threadIdx.x;
@@ -152,6 +174,11 @@ __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int 
 // Registers that prefetch a column's K aliases before the iteration scalars
 // are known; further grids continue in a loop.
 constexpr int kPrefetch = 4;
+// Loads issued together in the loops over long rows and further grids:
+// eight for FP32 pairs, six for FP64 pairs (what fits in the 64 registers of
+// eight waves per SIMD without spilling).
+template <typename P> struct BatchOf { static constexpr int value = 8; };
+template <> struct BatchOf<double2> { static constexpr int value = 6; };
 
 // In a batch, whether problem p still iterates, read before any operand is
 // loaded so that the workgroups of finished problems cost no memory traffic.
@@ -171,10 +198,10 @@ __device__ __forceinline__ bool live_problem(const CglsArgs& a, int p) {
 // computed in FP64, which tends to zero at the least-squares solution even
 // when the system is inconsistent (r itself does not).
 template <typename P, bool NR>
-__global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void cgls_rows_kernel(CglsArgs a, int rel) {
   __shared__ double sh[16];
   P* const rqv = static_cast<P*>(a.rq);
-  const P* const psv = static_cast<const P*>(a.ps);
   __shared__ int s_done;
   const RowBlock bd = a.rblk[blockIdx.x];            // uniform: one scalar load
   const int p = bd.prob;
@@ -183,25 +210,32 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) 
   // first workgroup sets the flag during this launch
   if (threadIdx.x == 0) s_done = a.done[p];
   const int base = a.state[0];
-  const double gpart = load_partials(a.part_s, bd.cblk_off, bd.ncblk);
   // operands that do not depend on this iteration's scalars; in a batch a
   // problem that has stopped issues none of them
   const int32_t row = bd.row0 + threadIdx.x;
   const bool active = row < bd.row_end && live_problem(a, p);
-  double2 rq_old = make_double2(0.0, 0.0);
+  // values stay raw (RawOf) until after the barrier, so that the loads are
+  // all in flight together
+  typedef typename RawOf<P>::type R;
+  const R* const rqr = static_cast<const R*>(a.rq);
+  const R* const psr = static_cast<const R*>(a.ps);
+  R rq_raw = raw_zero<R>();
   int4 e = make_int4(-1, -1, -1, -1);
   if (active) {
-    rq_old = to_d2(rqv[row]);
+    rq_raw = rqr[row];
     e = a.ell[row];
   }
-  const double2 z = make_double2(0.0, 0.0);
-  const double2 v0 = e.x >= 0 ? to_d2(psv[e.x]) : z;
-  const double2 v1 = e.y >= 0 ? to_d2(psv[e.y]) : z;
-  const double2 v2 = e.z >= 0 ? to_d2(psv[e.z]) : z;
-  const double2 v3 = e.w >= 0 ? to_d2(psv[e.w]) : z;
+  const R r0 = e.x >= 0 ? psr[e.x] : raw_zero<R>();
+  const R r1 = e.y >= 0 ? psr[e.y] : raw_zero<R>();
+  const R r2 = e.z >= 0 ? psr[e.z] : raw_zero<R>();
+  const R r3 = e.w >= 0 ? psr[e.w] : raw_zero<R>();
+  const double gpart = load_partials(a.part_s, bd.cblk_off, bd.ncblk);
   __syncthreads();
   if (s_done != 0) return;                           // problem converged or stopped
   const int k = base + rel;
+  // k0: first iteration of this run (0, or 1 for a mixed-precision round that
+  // continues the previous round's direction; see refine_cols_kernel)
+  const int k0 = a.state[1];
   double gprev = 1.0, g0 = 0.0, alpha_prev = 0.0;
   if (k > 0) {
     gprev = ring_gamma(a.ring, p, k - 1);
@@ -209,22 +243,19 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) 
     g0 = a.gamma0[p];
   }
   const double gamma = block_sum(gpart, sh);
-  double beta = 0.0;
-  bool stop;
-  if (k == 0) {
-    stop = !(gamma > 0.0);                           // zero (or non-finite) A^T b
-  } else {
-    beta = gamma / gprev;
-    stop = !(gamma > a.tol2 * g0);
-  }
+  const double beta = k > 0 ? gamma / gprev : 0.0;
+  // the first iteration only stops on a zero (or non-finite) normal residual
+  const bool stop = k == k0 ? !(gamma > 0.0) : !(gamma > a.tol2 * g0);
   if (bd.first && threadIdx.x == 0) {
     a.ring[p * 8 + (k & 3)] = gamma;
-    if (k == 0) a.gamma0[p] = gamma;
+    if (k == k0) a.gamma0[p] = gamma;
     if (stop) a.done[p] = k + 1;
   }
   if (stop) return;
   double qv = 0.0;
   if (active) {
+    const double2 rq_old = raw_d2(rq_raw);
+    const double2 v0 = raw_d2(r0), v1 = raw_d2(r1), v2 = raw_d2(r2), v3 = raw_d2(r3);
     // terms in perm order: p_k = s_k + beta p_{k-1} for each aliased column
     if (e.x >= 0) qv += fma(beta, v0.x, v0.y);
     if (e.y >= 0) qv += fma(beta, v1.x, v1.y);
@@ -232,9 +263,21 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) 
     if (e.w >= 0) qv += fma(beta, v3.x, v3.y);
     if (e.w < -1) {                                  // long row: rest of its run in perm
       const int32_t t1 = a.seg_off[row + 1];
-      for (int32_t t = -(e.w + 2); t < t1; ++t) {
-        const double2 v = to_d2(psv[a.perm[t]]);
-        qv += fma(beta, v.x, v.y);
+      constexpr int kBatch = BatchOf<P>::value;
+      for (int32_t t0 = -(e.w + 2); t0 < t1; t0 += kBatch) {
+        // kBatch independent index loads, then kBatch independent gathers,
+        // then the sums in perm order
+        int32_t jj[kBatch];
+        R vv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) jj[u] = t0 + u < t1 ? a.perm[t0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) vv[u] = jj[u] >= 0 ? psr[jj[u]] : raw_zero<R>();
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const double2 v = raw_d2(vv[u]);
+          if (jj[u] >= 0) qv += fma(beta, v.x, v.y);
+        }
       }
     }
     rqv[row] = make_pair<P>(NR ? 0.0 : fma(-alpha_prev, rq_old.y, rq_old.x), qv);
@@ -244,31 +287,33 @@ __global__ __launch_bounds__(kBlock) void cgls_rows_kernel(CglsArgs a, int rel) 
 }
 
 template <typename P, bool NR>
-__global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void cgls_cols_kernel(CglsArgs a, int rel) {
   __shared__ double sh[16];
-  const P* const rqv = static_cast<const P*>(a.rq);
   P* const psv = static_cast<P*>(a.ps);
   __shared__ int s_done;
   const ColBlock bd = a.cblk[blockIdx.x];
   const int p = bd.prob;
   if (threadIdx.x == 0) s_done = a.done[p];
   const int base = a.state[0];
-  const double dpart = load_partials(a.part_q, bd.rblk_off, bd.nrblk);
   const int32_t j = bd.col0 + threadIdx.x;
   const bool active = j < bd.col_end && live_problem(a, p);
   const int32_t jl = j - bd.col_off;
-  double2 ps_old = make_double2(0.0, 0.0);
-  double c_old = 0.0;
-  double2 g[kPrefetch];
-  if (active) {
-    ps_old = to_d2(psv[j]);
-    c_old = a.c[j];
-  }
+  // Unconditional loads from clamped indices (an idle lane reads the
+  // block's first column, shared by its whole wave), raw until after the
+  // barrier: the index loads and the gathers they feed are each issued
+  // together instead of one pair at a time.
+  typedef typename RawOf<P>::type R;
+  const R* const rqr = static_cast<const R*>(a.rq);
+  const int32_t jc = active ? j : bd.col0;
+  const int32_t jlc = jc - bd.col_off;
+  const R ps_raw = static_cast<const R*>(a.ps)[jc];
+  const double c_old = a.c[jc];
+  R g[kPrefetch];
 #pragma unroll
-  for (int l = 0; l < kPrefetch; ++l) {
-    g[l] = make_double2(0.0, 0.0);
-    if (active && l < bd.K) g[l] = to_d2(rqv[a.rowmap[bd.rmap_off + l * bd.n + jl]]);
-  }
+  for (int l = 0; l < kPrefetch; ++l)
+    g[l] = rqr[a.rowmap[bd.rmap_off + (l < bd.K ? l : 0) * bd.n + jlc]];
+  const double dpart = load_partials(a.part_q, bd.rblk_off, bd.nrblk);
   __syncthreads();
   if (s_done != 0) return;
   const int k = base + rel;
@@ -284,25 +329,35 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) 
   if (bd.first && threadIdx.x == 0) a.ring[p * 8 + 4 + (k & 3)] = alpha;
   double sv = 0.0;
   if (active) {
+    const double2 ps_old = raw_d2(ps_raw);
     const double pv = fma(beta, ps_old.x, ps_old.y);
     a.c[j] = fma(alpha, pv, c_old);
-    if (NR) {
-      double qs = 0.0;                               // (A^T q)_j
+    double qs = 0.0;                                 // NR: (A^T q)_j
 #pragma unroll
-      for (int l = 0; l < kPrefetch; ++l)
-        if (l < bd.K) qs += g[l].y;
-      for (int l = kPrefetch; l < bd.K; ++l)
-        qs += to_d2(rqv[a.rowmap[bd.rmap_off + l * bd.n + jl]]).y;
-      sv = fma(-alpha, qs, ps_old.y);
-    } else {
-#pragma unroll
-      for (int l = 0; l < kPrefetch; ++l)
-        if (l < bd.K) sv += fma(-alpha, g[l].y, g[l].x);
-      for (int l = kPrefetch; l < bd.K; ++l) {
-        const double2 v = to_d2(rqv[a.rowmap[bd.rmap_off + l * bd.n + jl]]);
-        sv += fma(-alpha, v.y, v.x);
+    for (int l = 0; l < kPrefetch; ++l) {
+      const double2 v = raw_d2(g[l]);
+      if (l < bd.K) {
+        if (NR) qs += v.y;
+        else sv += fma(-alpha, v.y, v.x);
       }
     }
+    // further grids kBatch at a time: independent loads, sums in grid order
+    constexpr int kBatch = BatchOf<P>::value;
+    for (int l0 = kPrefetch; l0 < bd.K; l0 += kBatch) {
+      R vv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        vv[u] = rqr[a.rowmap[bd.rmap_off + min(l0 + u, bd.K - 1) * bd.n + jl]];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const double2 v = raw_d2(vv[u]);
+        if (l0 + u < bd.K) {
+          if (NR) qs += v.y;
+          else sv += fma(-alpha, v.y, v.x);
+        }
+      }
+    }
+    if (NR) sv = fma(-alpha, qs, ps_old.y);
     psv[j] = make_pair<P>(pv, sv);
   }
   const double part = block_sum(sv * sv, sh);
@@ -313,9 +368,10 @@ __global__ __launch_bounds__(kBlock) void cgls_cols_kernel(CglsArgs a, int rel) 
 // r64 = b - A c in FP64 (c is FP64), q = 0; resets the round's iteration
 // state; problems already finished keep their stop flag.
 __global__ __launch_bounds__(kBlock) void refine_rows_kernel(CglsArgs a,
-                                                             const double* __restrict__ b) {
+                                                             const double* __restrict__ b,
+                                                             int start) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g == 0) a.state[0] = 0;
+  if (g == 0) { a.state[0] = start; a.state[1] = start; }
   if (g < a.nprob) { a.done[g] = a.outer_done[g]; a.flags[g] = 0; }
   const RowBlock bd = a.rblk[blockIdx.x];
   const int32_t row = bd.row0 + threadIdx.x;
@@ -335,19 +391,29 @@ __global__ __launch_bounds__(kBlock) void refine_rows_kernel(CglsArgs a,
   static_cast<float2*>(a.rq)[row] = make_float2((float)r, 0.0f);
 }
 
-// s64 = A^T r64 in FP64; (p, s) = (0, fp32(s64)); partials of ||fp32(s)||^2
-// (the round's CG start) and of ||s64||^2 (the FP64 normal residual).
-__global__ __launch_bounds__(kBlock) void refine_cols_kernel(CglsArgs a) {
+// s64 = A^T r64 in FP64 and s = fp32(s64); partials of ||s||^2 (the round's
+// CG start) and of ||s64||^2 (the FP64 normal residual).
+// A problem with gprev[p] > 0 continues its previous direction (a reliable
+// update: only the recurred residual is replaced by the true one): p is
+// kept and ring entry 0 receives gamma of the iteration before the previous
+// round stopped, so the round's first step (iteration 1) forms
+// p = s + (||s||^2 / gprev) p_old.  Otherwise the round restarts with p = 0.
+__global__ __launch_bounds__(kBlock) void refine_cols_kernel(CglsArgs a,
+                                                             const double* __restrict__ gprev) {
   __shared__ double sh[16];
   const ColBlock bd = a.cblk[blockIdx.x];
   const int32_t j = bd.col0 + threadIdx.x;
+  const bool cont = gprev[bd.prob] > 0.0;
+  // a restarting problem gets any finite positive entry (it multiplies p = 0)
+  if (bd.first && threadIdx.x == 0) a.ring[bd.prob * 8] = cont ? gprev[bd.prob] : 1.0;
   double s64 = 0.0, s32 = 0.0;
   if (j < bd.col_end) {
     const int32_t jl = j - bd.col_off;
     for (int l = 0; l < bd.K; ++l) s64 += a.r64[a.rowmap[bd.rmap_off + l * bd.n + jl]];
     const float sf = (float)s64;
     s32 = sf;
-    static_cast<float2*>(a.ps)[j] = make_float2(0.0f, sf);
+    float2* ps = static_cast<float2*>(a.ps);
+    ps[j] = make_float2(cont ? ps[j].x : 0.0f, sf);
   }
   const double p32 = block_sum(s32 * s32, sh);
   const double p64 = block_sum(s64 * s64, sh);
@@ -383,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void cgls_gamma_kernel(CglsArgs a, int k) {
 }
 
 __global__ void cgls_set_base_kernel(int32_t* state, int base) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) state[0] = base;
+  if (threadIdx.x == 0 && blockIdx.x == 0) { state[0] = base; state[1] = 0; }
 }
 
 __global__ void cgls_fill_i32_kernel(int32_t* v, int n, int value) {
@@ -445,12 +511,13 @@ hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_refine(const CglsArgs& a, const double* b, int round, double tol2_outer,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(refine_rows_kernel, dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, b);
+hipError_t launch_refine(const CglsArgs& a, const double* b, const double* gprev, int start,
+                         int round, double tol2_outer, hipStream_t s) {
+  hipLaunchKernelGGL(refine_rows_kernel, dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, b,
+                     start);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(refine_cols_kernel, dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(refine_cols_kernel, dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, gprev);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(refine_check_kernel, dim3((unsigned)a.nprob), dim3(kBlock), 0, s, a, round,

@@ -658,6 +658,8 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   FCT_HIP(dalloc(&w->d_gtrue, 2 * P, nullptr));
   FCT_HIP(dalloc(&w->d_outer, P, nullptr));
   FCT_HIP(hipHostMalloc((void**)&w->h_outer, sizeof(int32_t) * P, hipHostMallocDefault));
+  FCT_HIP(dalloc(&w->d_gprev, P, nullptr));
+  FCT_HIP(hipHostMalloc((void**)&w->h_gprev, sizeof(double) * P, hipHostMallocDefault));
   FCT_HIP(hipHostMalloc((void**)&w->h_gtrue, sizeof(double) * 2 * P, hipHostMallocDefault));
   FCT_HIP(dalloc(&w->d_part_q, p->nrblk, nullptr));
   FCT_HIP(dalloc(&w->d_part_s, p->ncblk, nullptr));
@@ -690,6 +692,8 @@ void fct_ws_destroy(fct_ws* w) {
   dfree(w->d_state_tmp); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
   dfree(w->d_outer);
   if (w->h_outer) (void)hipHostFree(w->h_outer);
+  dfree(w->d_gprev);
+  if (w->h_gprev) (void)hipHostFree(w->h_gprev);
   if (w->h_gtrue) (void)hipHostFree(w->h_gtrue);
   if (w->h_done) (void)hipHostFree(w->h_done);
   if (w->h_ring) (void)hipHostFree(w->h_ring);
@@ -829,7 +833,7 @@ static fct_status ensure_graph(fct_ws* ws, const CglsArgs& a, int chunk) {
 // predicts how many iterations remain and shortens the next chunk
 // accordingly, so few (early-exiting) launches run after the last problem
 // has converged.  Returns the number of iterations enqueued.
-static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, int maxit,
+static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, int k0, int maxit,
                             int chunk, bool use_graph, hipStream_t s, int* queued_out) {
   const int P = p->nprob;
   const int g = a.fp32 ? 1 : 0;
@@ -872,7 +876,7 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
     const int32_t* hd = ws->h_done + (size_t)sl * P;
     const double* hr = ws->h_ring + (size_t)sl * 8 * P;
     const double* hg0 = ws->h_gamma0 + (size_t)sl * P;
-    const int k = upto[sl] - 1;
+    const int k = k0 + upto[sl] - 1;             // last iteration of that chunk
     bool all_done = true;
     int need_max = -1;
     for (int q = 0; q < P; ++q) {
@@ -885,7 +889,7 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
         const double lrate = (std::log(glast[q]) - std::log(gprev[q])) / (double)(k - kprev[q]);
         const double need = (std::log(a.tol2 * g0) - std::log(glast[q])) / lrate;
         if (std::isfinite(need) && need >= 0.0) {
-          const double t = (double)k + need + 2.0;
+          const double t = (double)(k - k0) + need + 2.0;    // iterations of this run
           need_max = std::max(need_max, t < (double)maxit ? (int)t + 1 : maxit);
         } else {
           need_max = maxit;
@@ -978,7 +982,7 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   if (!mixed) {
     a.tol2 = o.tol * o.tol;
     FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
-    st = cgls_loop(p, ws, a, o.maxit, chunk, o.use_graph != 0, s, &last_queued);
+    st = cgls_loop(p, ws, a, 0, o.maxit, chunk, o.use_graph != 0, s, &last_queued);
     if (st != FCT_OK) return st;
     total_queued = last_queued;
     FCT_HIP(hipMemcpyAsync(fd, a.done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
@@ -993,32 +997,50 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     for (int q = 0; q < P; ++q) iters[(size_t)q] = fd[q] != 0 ? fd[q] - 1 : last_queued;
   } else {
     // FP32 CGLS rounds, each started from the FP64 residual of the FP64
-    // iterate; the outer test is the FP64 normal residual.
+    // iterate; the outer test is the FP64 normal residual.  A round after
+    // the first continues each problem's last direction (reliable update)
+    // unless o.restart_rounds is set or the problem broke down.
     a.tol2 = o.inner_tol * o.inner_tol;
     const double tol2_outer = o.tol * o.tol;
+    const bool restart = o.restart_rounds != 0;
     if (!o.warm_start) FCT_HIP(launch_fill_f64(d_c, p->n, 0.0, s));
     FCT_HIP(launch_fill_i32(ws->d_outer, P, 0, s));
+    FCT_HIP(launch_fill_f64(ws->d_gprev, P, 0.0, s));
     const int nround = o.mode == FCT_SOLVE_F32 ? 1 : o.max_refine;
     int budget = o.maxit;
+    int start = 0;
     for (int round = 0; round <= nround; ++round) {
-      FCT_HIP(launch_refine(a, d_b, round, tol2_outer, s));
+      FCT_HIP(launch_refine(a, d_b, ws->d_gprev, start, round, tol2_outer, s));
       FCT_HIP(hipMemcpyAsync(ws->h_outer, ws->d_outer, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
       FCT_HIP(hipStreamSynchronize(s));
       bool all = true;
       for (int q = 0; q < P; ++q) all &= ws->h_outer[q] != 0;
       if (all || round == nround || budget <= 0) break;
       if (o.mode == FCT_SOLVE_F32) a.tol2 = o.tol * o.tol;   // one round to the requested tol
-      st = cgls_loop(p, ws, a, budget, chunk, o.use_graph != 0, s, &last_queued);
+      st = cgls_loop(p, ws, a, start, budget, chunk, o.use_graph != 0, s, &last_queued);
       if (st != FCT_OK) return st;
       total_queued += last_queued;
       budget -= last_queued;
       FCT_HIP(hipMemcpyAsync(fd, a.done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipMemcpyAsync(fr, a.ring, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipMemcpyAsync(ws->h_flags, a.flags, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
       FCT_HIP(hipStreamSynchronize(s));
+      bool any_cont = false;
       for (int q = 0; q < P; ++q) {
+        ws->h_gprev[q] = 0.0;
         if (ws->h_outer[q] != 0) continue;
-        iters[(size_t)q] += fd[q] != 0 ? fd[q] - 1 : last_queued;
+        iters[(size_t)q] += fd[q] != 0 ? fd[q] - 1 - start : last_queued;
         rounds[(size_t)q] = round + 1;
+        // stopped at iteration ks after at least one step of this round: the
+        // next round continues p_{ks-1} with gamma_{ks-1} from the ring
+        const int ks = fd[q] - 1;
+        if (!restart && fd[q] != 0 && ws->h_flags[q] == 0 && ks - 1 >= start) {
+          const double gp = fr[q * 8 + ((ks - 1) & 3)];
+          if (gp > 0.0 && std::isfinite(gp)) { ws->h_gprev[q] = gp; any_cont = true; }
+        }
       }
+      start = any_cont ? 1 : 0;
+      FCT_HIP(hipMemcpyAsync(ws->d_gprev, ws->h_gprev, sizeof(double) * P, hipMemcpyHostToDevice, s));
     }
     FCT_HIP(hipMemcpyAsync(ws->h_outer, ws->d_outer, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
     FCT_HIP(hipMemcpyAsync(ws->h_gtrue, ws->d_gtrue, sizeof(double) * 2 * P, hipMemcpyDeviceToHost, s));

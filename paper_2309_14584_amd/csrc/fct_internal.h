@@ -183,8 +183,8 @@ hipError_t launch_cgls_set_base(int32_t* state, int base, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* v, int n, int value, hipStream_t s);
 hipError_t launch_fill_f64(double* v, int64_t n, double value, hipStream_t s);
 // one refinement round's start: r64 = b - A c, (p, s) = (0, A^T r), FP64 test
-hipError_t launch_refine(const CglsArgs& a, const double* b, int round, double tol2_outer,
-                         hipStream_t s);
+hipError_t launch_refine(const CglsArgs& a, const double* b, const double* gprev, int start,
+                         int round, double tol2_outer, hipStream_t s);
 int64_t segment_blocks(int64_t L);
 
 // batch construction: dst[i] = src[i] + add (i < count)
@@ -254,6 +254,8 @@ struct fct_ws {
   int32_t* d_outer = nullptr;      // [nprob]
   int32_t* h_outer = nullptr;      // pinned [nprob]
   double* h_gtrue = nullptr;       // pinned [2][nprob]
+  double* d_gprev = nullptr;       // [nprob] gamma before the previous round stopped (0: restart)
+  double* h_gprev = nullptr;       // pinned [nprob]
   double* d_part_q = nullptr;      // [nrblk]
   double* d_part_s = nullptr;      // [ncblk]
   double* d_ring = nullptr;        // [nprob][8]
