@@ -40,13 +40,14 @@ class Job:
 @dataclass
 class JobResult:
     id: int
-    c: np.ndarray
+    c: np.ndarray | None         # None when the job failed
     iterations: int
     converged: bool
     arrival: float
     admitted: float
     done: float
     slot: int
+    error: str | None = None
 
     @property
     def latency(self):
@@ -60,6 +61,7 @@ class _Stats:
     max_running: int = 0
     max_bytes: int = 0
     waits_for_memory: int = 0
+    failed: int = 0
 
 
 class Engine:
@@ -78,10 +80,13 @@ class Engine:
         self.budget = int(budget_bytes)
         self.stats = _Stats()
 
-    def run(self, jobs, clock=time.perf_counter, cancel=None):
+    def run(self, jobs, clock=time.perf_counter, cancel=None, fail_fast=False):
         """Serve ``jobs`` (arrival times relative to the start); returns the
         results in completion order.  ``cancel`` is an optional set of job
-        ids to drop if they have not been admitted yet."""
+        ids to drop if they have not been admitted yet.  A job whose executor
+        call raises frees its slot and memory and is reported with
+        ``error`` set; the other jobs run on (``fail_fast`` instead stops
+        admitting and raises once the running jobs have finished)."""
         cancel = cancel if cancel is not None else set()
         order = sorted(jobs, key=lambda j: (j.arrival, j.id))
         t0 = clock()
@@ -98,15 +103,16 @@ class Engine:
 
         def finished(job, slot, nbytes, t_adm, fut):
             nonlocal running
+            err = None
             try:
                 c, iters, conv = fut.result()
-            except BaseException as exc:        # noqa: BLE001 - handed to the caller
+            except BaseException as exc:        # noqa: BLE001 - reported per job
                 c, iters, conv = None, 0, False
+                err = f"{type(exc).__name__}: {exc}"
                 errors.append((job.id, exc))
             with lock:
-                if c is not None:
-                    results.append(JobResult(job.id, c, iters, conv, job.arrival, t_adm,
-                                             clock() - t0, slot))
+                results.append(JobResult(job.id, c, iters, conv, job.arrival, t_adm,
+                                         clock() - t0, slot, err))
                 free_slots.append(slot)
                 in_use[0] -= nbytes
                 running -= 1
@@ -145,7 +151,8 @@ class Engine:
                         fut.add_done_callback(
                             lambda f, job=job, slot=slot, need=need, t_adm=t_adm:
                             finished(job, slot, need, t_adm, f))
-                    if errors or (nxt >= len(order) and not queue and running == 0):
+                    if (fail_fast and errors) or (nxt >= len(order) and not queue
+                                                  and running == 0):
                         break
                     # sleep until the next arrival or a completion
                     wait = None
@@ -154,7 +161,8 @@ class Engine:
                     if not done_events:
                         lock.wait(timeout=wait if wait is not None else 0.05)
                     done_events.clear()
-        if errors:
+        self.stats.failed = len(errors)
+        if fail_fast and errors:
             jid, exc = errors[0]
             raise RuntimeError(f"job {jid} failed") from exc
         return results

@@ -420,3 +420,36 @@ def test_batched_workload_selected_grids_recover():
         plan = O.build_plan(p.support, p.grids)
         c, its, _ = O.lstsq_lsqr(plan, O.sparse_A(plan) @ p.coeffs)
         assert O.max_rel_err(c, p.coeffs) < 1e-10
+
+
+def test_single_node_dimensions_null_vector():
+    """prod_{i in I} (T_0 - T_1)(x_i) lies in the null space of every grid
+    with a single node (degree 0) in some dimension of I: the reason the
+    workloads let the oracle choose their grid counts.  Checked against A
+    built from its definition; adding a grid that resolves all of I removes
+    that null vector."""
+    S = W.total_degree_support(4, 3)
+    I = (0, 2)
+    c = np.zeros(len(S))
+    index = {tuple(r): j for j, r in enumerate(S.tolist())}
+    for a in (0, 1):
+        for b in (0, 1):
+            n = [0, 0, 0, 0]
+            n[I[0]], n[I[1]] = a, b
+            c[index[tuple(n)]] = (-1.0) ** (a + b)        # (T_0 - T_1) x (T_0 - T_1)
+    grids = np.array([[0, 5, 4, 3], [6, 2, 0, 4], [0, 3, 0, 5]], dtype=np.int32)
+    A = O.dense_A(O.build_plan(S, grids))
+    assert np.abs(A @ c).max() == 0.0
+    # the polynomial really vanishes on those grids (brute-force samples)
+    for g in grids:
+        assert np.abs(O.sample_planted(S, c, g)).max() < 1e-12
+    more = np.vstack([grids, [[2, 1, 3, 2]]]).astype(np.int32)
+    assert np.abs(O.dense_A(O.build_plan(S, more)) @ c).max() > 0.5
+
+
+def test_sampling_in_slabs_is_pointwise_identical():
+    g = [3, 4, 2, 5]
+    for fam, prm in [(W.FAMILY_GAUSS, np.concatenate([[0.8], np.linspace(-.3, .3, 4)])),
+                     (W.FAMILY_EXPCOS, np.linspace(0.2, 1.0, 8))]:
+        full = O.sample_function(fam, prm, g)
+        assert np.array_equal(full, O.sample_function(fam, prm, g, chunk=7))

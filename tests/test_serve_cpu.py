@@ -105,10 +105,48 @@ def test_fifo_head_blocks_under_memory_pressure():
     assert res[2].admitted >= res[1].admitted
 
 
-def test_executor_error_propagates():
+def test_failed_job_frees_its_slot_and_others_run_on():
+    ex = FakeExecutor(fail={2})
+    eng = Engine(ex, slots=1, budget_bytes=10)
+    res = {r.id: r for r in eng.run(_jobs([0.0, 0.0, 0.0, 0.01, 0.02], t=0.01, nbytes=10))}
+    assert sorted(res) == [0, 1, 2, 3, 4]
+    assert res[2].c is None and "planted failure" in res[2].error
+    for j in (0, 1, 3, 4):                 # unchanged by the failure
+        assert res[j].error is None and np.array_equal(res[j].c, np.full(3, float(j)))
+    assert eng.stats.failed == 1 and eng.stats.max_bytes <= 10
+
+
+def test_fail_fast_raises():
     ex = FakeExecutor(fail={2})
     with pytest.raises(RuntimeError, match="job 2"):
-        Engine(ex, slots=2).run(_jobs([0.0, 0.0, 0.0, 0.01], t=0.01))
+        Engine(ex, slots=2).run(_jobs([0.0, 0.0, 0.0, 0.01], t=0.01), fail_fast=True)
+
+
+class OracleExecutor:
+    """The same executor interface, backed by the oracle (small jobs)."""
+
+    def footprint(self, job):
+        return 1
+
+    def run(self, job, slot):
+        import oracle as O
+        p = job.problem
+        c, _, _ = O.fct_solve(p.support, p.grids, O.sample_problem(p), "qr")
+        return c, 0, True
+
+
+def test_oracle_executor_mix_matches_alone():
+    import oracle as O
+    import workloads as W
+    probs = [W.config1(), W.small_problem(3, 4, 6, 1, 6, 6, W.FAMILY_PLANTED),
+             W.small_problem(5, 3, 5, 2, 7, 3, W.FAMILY_EXPCOS)]
+    alone = [OracleExecutor().run(Job(i, p, 0.0), 0)[0] for i, p in enumerate(probs)]
+    jobs = [Job(i, probs[i % 3], 0.001 * i) for i in range(9)]
+    res = Engine(OracleExecutor(), slots=3).run(jobs)
+    assert len(res) == 9
+    for r in res:
+        assert np.array_equal(r.c, alone[r.id % 3])
+    assert O.max_rel_err(alone[0], probs[0].coeffs) < 1e-12
 
 
 def test_cancel_drops_waiting_jobs():
