@@ -97,7 +97,9 @@ typedef enum fct_solve_mode {
                                previous round's search direction unless
                                restart_rounds is set; stops on the FP64 normal
                                residual */
-  FCT_SOLVE_F32 = 2         /* a single such round, to tol (default 2e-7) */
+  FCT_SOLVE_F32 = 2         /* a single such round, to tol (default 2e-7) on its own
+                               FP32 normal residual; rel_normal_residual reports the
+                               FP64 one */
 } fct_solve_mode;
 
 /* Plan creation flags. */

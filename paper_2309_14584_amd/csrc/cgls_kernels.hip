@@ -39,14 +39,18 @@
 // overwriting.  The iteration number is a device-side base plus a
 // launch-time offset, which lets a fixed chunk of iterations be captured
 // once in a HIP graph and replayed.
+#include <algorithm>
+
 #include "fct_internal.h"
 
 namespace fct {
 namespace {
 
-// Sum over the workgroup; every thread gets the same value.  Wave sums use a
-// xor butterfly (each lane adds the same two operands as its partner, so all
-// lanes agree bit for bit), then wave 0 adds the wave sums in order.
+// Sum over the workgroup (up to 16 waves); every thread gets the same value.
+// Wave sums use a xor butterfly (each lane adds the same two operands as its
+// partner, so all lanes agree bit for bit), then thread 0 adds the wave sums
+// in order.  `sh` holds kShSlots doubles.
+constexpr int kShSlots = 17;
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int wave = threadIdx.x >> 6;
@@ -55,10 +59,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   if (threadIdx.x == 0) {
     double r = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
-    sh[8] = r;
+    sh[16] = r;
   }
   __syncthreads();
-  const double r = sh[8];
+  const double r = sh[16];
   __syncthreads();
   return r;
 }
@@ -76,6 +80,30 @@ __device__ __forceinline__ double load_partials(const double* __restrict__ part,
   }
   double v = 0.0;
   for (int32_t i = threadIdx.x; i < np; i += blockDim.x) v += part[off + i];
+  return v;
+}
+
+// The partial of ||q||^2 of row block b is the sum of its four per-wave
+// partials, in wave order; this thread's share of a problem's row blocks,
+// taken as load_partials takes per-block partials.
+__device__ __forceinline__ double row_block_partial(const double* __restrict__ part, int32_t b) {
+  const double* w = part + 4 * (int64_t)b;
+  return ((w[0] + w[1]) + w[2]) + w[3];
+}
+__device__ __forceinline__ double load_row_partials(const double* __restrict__ part, int32_t off,
+                                                    int32_t np) {
+  if (np <= (int32_t)blockDim.x) {
+    const int32_t i = (int32_t)threadIdx.x < np ? (int32_t)threadIdx.x : np - 1;
+    const double v = row_block_partial(part, off + i);
+    return (int32_t)threadIdx.x < np ? v : 0.0;
+  }
+  double v = 0.0;
+  for (int32_t i = threadIdx.x; i < np; i += blockDim.x) v += row_block_partial(part, off + i);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
@@ -102,6 +130,24 @@ __device__ __forceinline__ double2 raw_d2(unsigned long long v) {
   return make_double2(f.x, f.y);
 }
 template <typename R> __device__ __forceinline__ R raw_zero() { return R{}; }
+// What the column kernel gathers per row: the (r, q) pair as loaded, or in
+// the FP32 rounds q alone (float); row_d2 widens it to (r, q).
+template <bool NR, typename R> struct RowGather { typedef R type; };
+template <typename R> struct RowGather<true, R> { typedef float type; };
+__device__ __forceinline__ double2 row_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 row_d2(unsigned long long v) { return raw_d2(v); }
+__device__ __forceinline__ double2 row_d2(float q) { return make_double2(0.0, (double)q); }
+
+// p = s + beta p_prev in FP64, rounded to the pair's storage precision: the
+// FP32 rounds use the FP32 value of p everywhere (in q = A p, in the update
+// of c and in the next direction), as a unit that stages p in LDS does.
+template <typename P> __device__ __forceinline__ double direction(double beta, double2 v);
+template <> __device__ __forceinline__ double direction<double2>(double beta, double2 v) {
+  return fma(beta, v.x, v.y);
+}
+template <> __device__ __forceinline__ double direction<float2>(double beta, double2 v) {
+  return (double)(float)fma(beta, v.x, v.y);
+}
 
 template <typename P> __device__ __forceinline__ P make_pair(double x, double y);
 template <> __device__ __forceinline__ double2 make_pair<double2>(double x, double y) {
@@ -156,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void cgls_init_rows_kernel(CglsArgs a,
 
 // s_0 = A^T r_0, p = 0, c = 0 unless warm, partials of ||s_0||^2.
 __global__ __launch_bounds__(kBlock) void cgls_init_cols_kernel(CglsArgs a, int warm) {
-  __shared__ double sh[16];
+  __shared__ double sh[kShSlots];
   const ColBlock bd = a.cblk[blockIdx.x];
   const int32_t j = bd.col0 + threadIdx.x;
   double sv = 0.0;
@@ -200,7 +246,7 @@ __device__ __forceinline__ bool live_problem(const CglsArgs& a, int p) {
 template <typename P, bool NR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void cgls_rows_kernel(CglsArgs a, int rel) {
-  __shared__ double sh[16];
+  __shared__ double sh[kShSlots];
   P* const rqv = static_cast<P*>(a.rq);
   __shared__ int s_done;
   const RowBlock bd = a.rblk[blockIdx.x];            // uniform: one scalar load
@@ -257,10 +303,10 @@ void cgls_rows_kernel(CglsArgs a, int rel) {
     const double2 rq_old = raw_d2(rq_raw);
     const double2 v0 = raw_d2(r0), v1 = raw_d2(r1), v2 = raw_d2(r2), v3 = raw_d2(r3);
     // terms in perm order: p_k = s_k + beta p_{k-1} for each aliased column
-    if (e.x >= 0) qv += fma(beta, v0.x, v0.y);
-    if (e.y >= 0) qv += fma(beta, v1.x, v1.y);
-    if (e.z >= 0) qv += fma(beta, v2.x, v2.y);
-    if (e.w >= 0) qv += fma(beta, v3.x, v3.y);
+    if (e.x >= 0) qv += direction<P>(beta, v0);
+    if (e.y >= 0) qv += direction<P>(beta, v1);
+    if (e.z >= 0) qv += direction<P>(beta, v2);
+    if (e.w >= 0) qv += direction<P>(beta, v3);
     if (e.w < -1) {                                  // long row: rest of its run in perm
       const int32_t t1 = a.seg_off[row + 1];
       constexpr int kBatch = BatchOf<P>::value;
@@ -276,20 +322,23 @@ void cgls_rows_kernel(CglsArgs a, int rel) {
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
           const double2 v = raw_d2(vv[u]);
-          if (jj[u] >= 0) qv += fma(beta, v.x, v.y);
+          if (jj[u] >= 0) qv += direction<P>(beta, v);
         }
       }
     }
-    rqv[row] = make_pair<P>(NR ? 0.0 : fma(-alpha_prev, rq_old.y, rq_old.x), qv);
+    if (NR) static_cast<float*>(a.rq)[row] = (float)qv;     // q alone, FP32
+    else rqv[row] = make_pair<P>(fma(-alpha_prev, rq_old.y, rq_old.x), qv);
   }
-  const double part = block_sum(qv * qv, sh);
-  if (threadIdx.x == 0) a.part_q[blockIdx.x] = part;
+  // per-wave partials of ||q||^2 (no barrier: the consumer adds the four
+  // waves of each block in order)
+  const double w = wave_sum(qv * qv);
+  if ((threadIdx.x & 63) == 0) a.part_q[4 * (int64_t)bd.pslot + (threadIdx.x >> 6)] = w;
 }
 
 template <typename P, bool NR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void cgls_cols_kernel(CglsArgs a, int rel) {
-  __shared__ double sh[16];
+  __shared__ double sh[kShSlots];
   P* const psv = static_cast<P*>(a.ps);
   __shared__ int s_done;
   const ColBlock bd = a.cblk[blockIdx.x];
@@ -304,16 +353,17 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
   // barrier: the index loads and the gathers they feed are each issued
   // together instead of one pair at a time.
   typedef typename RawOf<P>::type R;
-  const R* const rqr = static_cast<const R*>(a.rq);
+  typedef typename RowGather<NR, R>::type G;
+  const G* const rqg = static_cast<const G*>(a.rq);
   const int32_t jc = active ? j : bd.col0;
   const int32_t jlc = jc - bd.col_off;
   const R ps_raw = static_cast<const R*>(a.ps)[jc];
   const double c_old = a.c[jc];
-  R g[kPrefetch];
+  G g[kPrefetch];
 #pragma unroll
   for (int l = 0; l < kPrefetch; ++l)
-    g[l] = rqr[a.rowmap[bd.rmap_off + (l < bd.K ? l : 0) * bd.n + jlc]];
-  const double dpart = load_partials(a.part_q, bd.rblk_off, bd.nrblk);
+    g[l] = rqg[a.rowmap[bd.rmap_off + (l < bd.K ? l : 0) * bd.n + jlc]];
+  const double dpart = load_row_partials(a.part_q, bd.rblk_off, bd.nrblk);
   __syncthreads();
   if (s_done != 0) return;
   const int k = base + rel;
@@ -330,12 +380,12 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
   double sv = 0.0;
   if (active) {
     const double2 ps_old = raw_d2(ps_raw);
-    const double pv = fma(beta, ps_old.x, ps_old.y);
+    const double pv = direction<P>(beta, ps_old);
     a.c[j] = fma(alpha, pv, c_old);
     double qs = 0.0;                                 // NR: (A^T q)_j
 #pragma unroll
     for (int l = 0; l < kPrefetch; ++l) {
-      const double2 v = raw_d2(g[l]);
+      const double2 v = row_d2(g[l]);
       if (l < bd.K) {
         if (NR) qs += v.y;
         else sv += fma(-alpha, v.y, v.x);
@@ -344,13 +394,13 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
     // further grids kBatch at a time: independent loads, sums in grid order
     constexpr int kBatch = BatchOf<P>::value;
     for (int l0 = kPrefetch; l0 < bd.K; l0 += kBatch) {
-      R vv[kBatch];
+      G vv[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u)
-        vv[u] = rqr[a.rowmap[bd.rmap_off + min(l0 + u, bd.K - 1) * bd.n + jl]];
+        vv[u] = rqg[a.rowmap[bd.rmap_off + min(l0 + u, bd.K - 1) * bd.n + jl]];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const double2 v = raw_d2(vv[u]);
+        const double2 v = row_d2(vv[u]);
         if (l0 + u < bd.K) {
           if (NR) qs += v.y;
           else sv += fma(-alpha, v.y, v.x);
@@ -364,9 +414,139 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
   if (threadIdx.x == 0) a.part_s[blockIdx.x] = part;
 }
 
+// ---- FP32 rounds of a batch: q = A p from LDS ----
+// One workgroup of kLdsBlock threads per unit (up to kUnitRows consecutive
+// rows of one problem).  The problem's p = fp32(s + beta p_prev) is staged in
+// LDS once, then each row sums its entries from LDS.  Every value and every
+// reduction is formed exactly as in cgls_rows_kernel<float2, true>: gamma
+// from the column partials by the first 256 threads in the 256-thread order,
+// the per-row sums in perm order, and the per-wave partials of ||q||^2 of
+// each 256-row block with the same butterflies, written to that block's
+// slots.  So a problem gives the same bits
+// whether its rows run here (in a batch) or in row blocks (alone).
+constexpr int kUnitChunks = 6;          // rows per thread in flight (chunks of kLdsBlock rows)
+
+__global__ __launch_bounds__(kLdsBlock) void cgls_rows_unit_kernel(CglsArgs a, int rel) {
+  extern __shared__ float lds_p[];                   // [lds_cap]
+  __shared__ double sh[kShSlots];
+  __shared__ int s_done;
+  const RowUnit u = a.units[blockIdx.x];
+  const int p = u.prob;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_done = a.done[p];
+  const int base = a.state[0];
+  // this thread's share of the column partials, as a 256-thread block takes it
+  double gpart = 0.0;
+  if (tid < kBlock)
+    for (int32_t i = tid; i < u.ncblk; i += kBlock) gpart += a.part_s[u.cblk_off + i];
+  __syncthreads();
+  if (s_done != 0) return;
+  const int k = base + rel;
+  const int k0 = a.state[1];
+  double gprev = 1.0, g0 = 0.0;
+  if (k > 0) {
+    gprev = ring_gamma(a.ring, p, k - 1);
+    g0 = a.gamma0[p];
+  }
+  // gamma: butterflies in waves 0..3, then their four sums in order
+  {
+    const double w = wave_sum(gpart);
+    if ((tid & 63) == 0 && tid < kBlock) sh[tid >> 6] = w;
+    __syncthreads();
+    if (tid == 0) sh[16] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+  }
+  const double gamma = sh[16];
+  const double beta = k > 0 ? gamma / gprev : 0.0;
+  const bool stop = k == k0 ? !(gamma > 0.0) : !(gamma > a.tol2 * g0);
+  if (u.first && tid == 0) {
+    a.ring[p * 8 + (k & 3)] = gamma;
+    if (k == k0) a.gamma0[p] = gamma;
+    if (stop) a.done[p] = k + 1;
+  }
+  if (stop) return;
+
+  // stage p of the problem's columns
+  const unsigned long long* psr = static_cast<const unsigned long long*>(a.ps);
+  // eight coalesced loads in flight per thread, then their LDS stores
+  for (int32_t j0 = 0; j0 < u.n; j0 += 8 * kLdsBlock) {
+    unsigned long long raw[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int32_t j = j0 + v * kLdsBlock + tid;
+      raw[v] = psr[u.col_off + (j < u.n ? j : 0)];
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int32_t j = j0 + v * kLdsBlock + tid;
+      const double2 x = raw_d2(raw[v]);
+      if (j < u.n) lds_p[j] = (float)fma(beta, x.x, x.y);
+    }
+  }
+  __syncthreads();
+
+  float* const q = static_cast<float*>(a.rq);
+  const int32_t rows_per_round = kUnitChunks * kLdsBlock;
+  // the 16-bit ELL entries of kUnitChunks rows per thread, all in flight;
+  // the next round's are loaded before this round's sums are formed
+  uint4 en[kUnitChunks];
+#pragma unroll
+  for (int c = 0; c < kUnitChunks; ++c) {
+    const int32_t row = u.row0 + c * kLdsBlock + tid;
+    en[c] = a.ell16[row < u.row_end ? row : u.row0];
+  }
+  for (int32_t r0 = u.row0; r0 < u.row_end; r0 += rows_per_round) {
+    uint4 e[kUnitChunks];
+#pragma unroll
+    for (int c = 0; c < kUnitChunks; ++c) {
+      e[c] = en[c];
+      const int32_t row = r0 + rows_per_round + c * kLdsBlock + tid;
+      en[c] = a.ell16[row < u.row_end ? row : u.row0];
+    }
+    double qv[kUnitChunks];
+#pragma unroll
+    for (int c = 0; c < kUnitChunks; ++c) {
+      const int32_t row = r0 + c * kLdsBlock + tid;
+      qv[c] = 0.0;
+      if (row < u.row_end) {
+        const uint32_t w[4] = {e[c].x, e[c].y, e[c].z, e[c].w};
+        // slots in perm order; 0xFFFF empty, slot 7 = 0xFFFE: the run goes on
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t v = (w[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+          if (v < 0xFFFEu) qv[c] += (double)lds_p[v];
+        }
+        if ((w[3] >> 16) == 0xFFFEu) {               // long row: perm from entry 7 on
+          const int32_t t1 = a.seg_off[row + 1];
+          for (int32_t t0 = a.seg_off[row] + 7; t0 < t1; t0 += 16) {
+            int32_t jj[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) jj[v] = a.perm[min(t0 + v, t1 - 1)];
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+              if (t0 + v < t1) qv[c] += (double)lds_p[jj[v] - u.col_off];
+          }
+        }
+        q[row] = (float)qv[c];
+      }
+    }
+    // per-wave partials of ||q||^2 into the slots of the row blocks, as
+    // the row-block kernel writes them (a wave past the unit's end but in
+    // its last block writes 0)
+#pragma unroll
+    for (int c = 0; c < kUnitChunks; ++c) {
+      const double w = wave_sum(qv[c] * qv[c]);
+      const int32_t wrow = r0 + c * kLdsBlock + (tid & ~63);     // the wave's first row
+      const int32_t blk = (wrow - u.row0) / kBlock;
+      if ((tid & 63) == 0 && u.row0 + blk * kBlock < u.row_end)
+        a.part_q[4 * (int64_t)(u.pslot + blk) + ((wrow - u.row0) % kBlock) / 64] = w;
+    }
+  }
+}
+
 // ---- mixed precision: FP32 CGLS rounds with FP64 residual refinement ----
-// r64 = b - A c in FP64 (c is FP64), q = 0; resets the round's iteration
-// state; problems already finished keep their stop flag.
+// r64 = b - A c in FP64 (c is FP64); resets the round's iteration state;
+// problems already finished keep their stop flag.
 __global__ __launch_bounds__(kBlock) void refine_rows_kernel(CglsArgs a,
                                                              const double* __restrict__ b,
                                                              int start) {
@@ -386,9 +566,7 @@ __global__ __launch_bounds__(kBlock) void refine_rows_kernel(CglsArgs a,
     const int32_t t1 = a.seg_off[row + 1];
     for (int32_t t = -(e.w + 2); t < t1; ++t) acc += a.c[a.perm[t]];
   }
-  const double r = b[row] - acc;
-  a.r64[row] = r;
-  static_cast<float2*>(a.rq)[row] = make_float2((float)r, 0.0f);
+  a.r64[row] = b[row] - acc;
 }
 
 // s64 = A^T r64 in FP64 and s = fp32(s64); partials of ||s||^2 (the round's
@@ -400,7 +578,7 @@ __global__ __launch_bounds__(kBlock) void refine_rows_kernel(CglsArgs a,
 // p = s + (||s||^2 / gprev) p_old.  Otherwise the round restarts with p = 0.
 __global__ __launch_bounds__(kBlock) void refine_cols_kernel(CglsArgs a,
                                                              const double* __restrict__ gprev) {
-  __shared__ double sh[16];
+  __shared__ double sh[kShSlots];
   const ColBlock bd = a.cblk[blockIdx.x];
   const int32_t j = bd.col0 + threadIdx.x;
   const bool cont = gprev[bd.prob] > 0.0;
@@ -425,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void refine_cols_kernel(CglsArgs a,
 // it has dropped to tol_outer^2 of the reference (or is zero / not finite).
 __global__ __launch_bounds__(kBlock) void refine_check_kernel(CglsArgs a, int round,
                                                               double tol2_outer) {
-  __shared__ double sh[16];
+  __shared__ double sh[kShSlots];
   const int p = blockIdx.x;
   const ProbInfo pi = a.prob[p];
   const double g = block_sum(load_partials(a.part_true, pi.cblk_off, pi.ncblk), sh);
@@ -441,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void refine_check_kernel(CglsArgs a, int ro
 // gamma of the current column partials into ring entry k, for every problem
 // that did not stop (one workgroup per problem).
 __global__ __launch_bounds__(kBlock) void cgls_gamma_kernel(CglsArgs a, int k) {
-  __shared__ double sh[16];
+  __shared__ double sh[kShSlots];
   const int p = blockIdx.x;
   const ProbInfo pi = a.prob[p];
   const double gamma = block_sum(load_partials(a.part_s, pi.cblk_off, pi.ncblk), sh);
@@ -496,11 +674,42 @@ hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipSt
 }
 
 hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s) {
-  if (a.fp32)
-    hipLaunchKernelGGL((cgls_rows_kernel<float2, true>), dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, rel);
-  else
+  if (a.fp32) {
+    // a batch's LDS units, then the row blocks of the remaining problems
+    if (a.nunits > 0) {
+      hipLaunchKernelGGL(cgls_rows_unit_kernel, dim3((unsigned)a.nunits), dim3(kLdsBlock),
+                         (size_t)a.lds_bytes, s, a, rel);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (a.nrblk32 > 0) {
+      CglsArgs b = a;
+      b.rblk = a.rblk32;
+      hipLaunchKernelGGL((cgls_rows_kernel<float2, true>), dim3((unsigned)a.nrblk32), dim3(kBlock),
+                         0, s, b, rel);
+    }
+  } else {
     hipLaunchKernelGGL((cgls_rows_kernel<double2, false>), dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, rel);
+  }
   return hipGetLastError();
+}
+
+int32_t lds_unit_capacity(int device) {
+  int maxsh = 0;
+  if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+    return 0;
+  // static LDS of the unit kernel: sh, s_done
+  const int avail = maxsh - (int)(sizeof(double) * kShSlots) - 64;
+  int cap = avail / (int)sizeof(float);
+  cap = std::min(cap, 40960);
+  if (cap < 1024) return 0;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&cgls_rows_unit_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          cap * (int)sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return cap;
 }
 
 hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s) {

@@ -169,6 +169,7 @@ void destroy_plan(fct_plan* p) {
   dfree(p->d_alias); dfree(p->d_perm); dfree(p->d_seg_off); dfree(p->d_bin_id);
   dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_ell); dfree(p->d_nodes); dfree(p->d_cmat);
   dfree(p->d_emat); dfree(p->d_rblk); dfree(p->d_cblk); dfree(p->d_prob);
+  dfree(p->d_units); dfree(p->d_rblk32); dfree(p->d_ell16);
   free_levels(p->fwd);
   free_levels(p->fwd_full);
   free_levels(p->inv);
@@ -215,16 +216,24 @@ fct_status build_dct_levels(fct_plan* p) {
 // Row and column blocks of every problem, and the problem table.  Problem
 // p's rows (columns) are cut into blocks of kBlock starting at its own first
 // row (column), so the blocking -- and with it every reduction order -- of a
-// problem does not depend on the other problems of a batch.
+// problem does not depend on the other problems of a batch.  In a batch, the
+// FP32 rounds of every problem whose columns fit in a unit's LDS run on LDS
+// units of up to kUnitRows rows instead (their per-row sums are in the same
+// order, so a problem gives the same bits alone and in the batch); the
+// other problems keep their row blocks (rb32).
 fct_status build_blocks(fct_plan* p) {
-  std::vector<RowBlock> rb;
+  std::vector<RowBlock> rb, rb32;
   std::vector<ColBlock> cb;
+  std::vector<RowUnit> units;
+  p->lds_cap = p->nprob > 1 ? lds_unit_capacity(p->device) : 0;
   for (int32_t q = 0; q < p->nprob; ++q) {
     ProbInfo& pi = p->probs[(size_t)q];
     pi.rblk_off = (int32_t)rb.size();
     pi.nrblk = (int32_t)ceil_div(pi.M, kBlock);
     pi.cblk_off = (int32_t)cb.size();
     pi.ncblk = (int32_t)ceil_div(pi.n, kBlock);
+    const bool lds = pi.n <= p->lds_cap;
+    const int32_t nunit = lds ? (int32_t)ceil_div(pi.M, kUnitRows) : 0;
     for (int32_t b = 0; b < pi.nrblk; ++b) {
       RowBlock r;
       std::memset(&r, 0, sizeof(r));
@@ -234,7 +243,23 @@ fct_status build_blocks(fct_plan* p) {
       r.cblk_off = pi.cblk_off;
       r.ncblk = pi.ncblk;
       r.first = b == 0;
+      r.pslot = (int32_t)rb.size();
       rb.push_back(r);
+      if (!lds) rb32.push_back(r);
+    }
+    for (int32_t u = 0; u < nunit; ++u) {
+      RowUnit t;
+      std::memset(&t, 0, sizeof(t));
+      t.prob = q;
+      t.row0 = pi.row_off + u * kUnitRows;
+      t.row_end = std::min(pi.row_off + pi.M, t.row0 + kUnitRows);
+      t.first = u == 0;
+      t.pslot = pi.rblk_off + u * (kUnitRows / kBlock);
+      t.cblk_off = pi.cblk_off;
+      t.ncblk = pi.ncblk;
+      t.col_off = pi.col_off;
+      t.n = pi.n;
+      units.push_back(t);
     }
     for (int32_t b = 0; b < pi.ncblk; ++b) {
       ColBlock c;
@@ -266,6 +291,24 @@ fct_status build_blocks(fct_plan* p) {
   FCT_HIP(hipMemcpy(p->d_cblk, cb.data(), sizeof(ColBlock) * cb.size(), hipMemcpyHostToDevice));
   FCT_HIP(hipMemcpy(p->d_prob, p->probs.data(), sizeof(ProbInfo) * p->probs.size(),
                     hipMemcpyHostToDevice));
+  p->nunits = (int64_t)units.size();
+  p->nrblk32 = (int64_t)rb32.size();
+  if (p->nunits > 0) {
+    FCT_HIP(dalloc(&p->d_units, p->nunits, bytes));
+    FCT_HIP(hipMemcpy(p->d_units, units.data(), sizeof(RowUnit) * units.size(),
+                      hipMemcpyHostToDevice));
+    FCT_HIP(dalloc(&p->d_ell16, p->M, bytes));
+    for (const ProbInfo& pi : p->probs)
+      if (pi.n <= p->lds_cap)
+        FCT_HIP(launch_ell16(p->d_seg_off, p->d_perm, pi.row_off, pi.M, pi.col_off, p->d_ell16,
+                             nullptr));
+    FCT_HIP(hipDeviceSynchronize());
+  }
+  if (p->nrblk32 > 0) {
+    FCT_HIP(dalloc(&p->d_rblk32, p->nrblk32, bytes));
+    FCT_HIP(hipMemcpy(p->d_rblk32, rb32.data(), sizeof(RowBlock) * rb32.size(),
+                      hipMemcpyHostToDevice));
+  }
   return FCT_OK;
 }
 
@@ -661,7 +704,7 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   FCT_HIP(dalloc(&w->d_gprev, P, nullptr));
   FCT_HIP(hipHostMalloc((void**)&w->h_gprev, sizeof(double) * P, hipHostMallocDefault));
   FCT_HIP(hipHostMalloc((void**)&w->h_gtrue, sizeof(double) * 2 * P, hipHostMallocDefault));
-  FCT_HIP(dalloc(&w->d_part_q, p->nrblk, nullptr));
+  FCT_HIP(dalloc(&w->d_part_q, 4 * p->nrblk, nullptr));   // one per wave of a row block
   FCT_HIP(dalloc(&w->d_part_s, p->ncblk, nullptr));
   FCT_HIP(dalloc(&w->d_ring, 8 * P, nullptr));
   FCT_HIP(dalloc(&w->d_gamma0, P, nullptr));
@@ -964,6 +1007,9 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   CglsArgs a;
   std::memset(&a, 0, sizeof(a));
   a.rblk = p->d_rblk; a.cblk = p->d_cblk; a.prob = p->d_prob;
+  a.units = p->d_units; a.nunits = p->nunits; a.ell16 = p->d_ell16;
+  a.rblk32 = p->d_rblk32; a.nrblk32 = p->nrblk32;
+  a.lds_bytes = p->lds_cap * (int32_t)sizeof(float);
   a.nrblk = p->nrblk; a.ncblk = p->ncblk; a.nprob = P;
   a.ell = p->d_ell; a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.rowmap = p->d_rowmap;
   a.rq = ws->d_rq; a.ps = ws->d_ps; a.c = d_c; a.fp32 = mixed ? 1 : 0;
@@ -1067,7 +1113,11 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
       g0 = ws->h_gtrue[q];
       gk = ws->h_gtrue[P + q];
       r.converged = (ws->h_outer[q] != 0 && std::isfinite(gk)) ? 1 : 0;
-      if (o.mode == FCT_SOLVE_F32) r.converged = gk <= o.tol * o.tol * g0 ? 1 : 0;
+      // pure FP32: its one round met the tolerance on its own (FP32)
+      // normal residual, or the FP64 normal residual is below it
+      if (o.mode == FCT_SOLVE_F32)
+        r.converged = (gk <= o.tol * o.tol * g0 ||
+                       (rounds[(size_t)q] > 0 && fd[q] != 0 && ws->h_flags[q] == 0)) ? 1 : 0;
       r.refinements = rounds[(size_t)q];
     }
     r.iterations = it;

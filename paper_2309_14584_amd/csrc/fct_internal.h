@@ -111,20 +111,35 @@ struct RowBlock {
   int32_t cblk_off;   // the problem's column blocks [cblk_off, cblk_off + ncblk)
   int32_t ncblk;
   int32_t first;      // 1 for the problem's first row block (writes its scalars)
-  int32_t pad0, pad1;
+  int32_t pslot;      // slot of this block's partials of ||q||^2 (4 per block)
+  int32_t pad1;
 };
 struct ColBlock {
   int32_t prob;
   int32_t col0;       // first global column of the block
   int32_t col_end;
   int32_t col_off;    // first global column of the problem
-  int32_t rblk_off;   // the problem's row blocks
-  int32_t nrblk;
+  int32_t rblk_off;   // first slot of the problem's row partials
+  int32_t nrblk;      // row partials of the FP64 row kernel
   int32_t K;          // grids of the problem
   int32_t n;          // columns of the problem
   int32_t rmap_off;   // offset of the problem's rowmap block [K][n]
   int32_t first;
   int32_t pad0, pad1;
+};
+// In a batch, FP32 rounds compute q = A p for every problem whose p vector
+// fits in LDS with one workgroup of kLdsBlock threads per unit of up to
+// kUnitRows rows: the unit stages p once and gathers from LDS.
+constexpr int kLdsBlock = 1024;
+constexpr int kUnitRows = 16384;
+struct RowUnit {
+  int32_t prob;
+  int32_t row0, row_end;   // global rows of the unit
+  int32_t first;           // 1 for the problem's first unit
+  int32_t pslot;           // first row-partial slot of the unit (its first row block)
+  int32_t cblk_off, ncblk; // the problem's column partials
+  int32_t col_off, n;      // the problem's columns
+  int32_t pad0, pad1, pad2;
 };
 struct ProbInfo {
   int32_t row_off, M;     // global rows of the problem
@@ -153,11 +168,11 @@ struct CglsArgs {
   const int32_t* seg_off;
   const int32_t* perm;
   const int32_t* rowmap;
-  void* rq;           // [M] (r, q) per row: double2, or float2 when fp32
+  void* rq;           // [M] (r, q) per row as double2; FP32 rounds: q as float
   void* ps;           // [n] (p, s) per column: double2, or float2 when fp32
   int32_t fp32;       // nonzero: FP32 storage of (r, q) and (p, s)
   double* c;          // [n]
-  double* part_q;     // [nrblk]
+  double* part_q;     // [4 nrblk] ||q||^2 per wave of each row block
   double* part_s;     // [ncblk]
   double* ring;       // [nprob][8]: gamma ring (k mod 4), alpha ring (k mod 4)
   double* gamma0;     // [nprob] ||A^T r_0||^2
@@ -171,6 +186,13 @@ struct CglsArgs {
   double* gtrue0;     // [nprob] FP64 ||A^T r||^2 of round 0
   double* gtrue;      // [nprob] FP64 ||A^T r||^2 of the latest round
   int32_t* outer_done;// [nprob] round+1 at which the problem finished, 0 while refining
+  // FP32 rounds of a batch: LDS units, and the row blocks of the other problems
+  const uint4* ell16;   // [M] 16-bit local-column ELL of the units' rows
+  const RowUnit* units;
+  int64_t nunits;
+  const RowBlock* rblk32;
+  int64_t nrblk32;
+  int32_t lds_bytes;  // dynamic LDS of the unit kernel
 };
 hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipStream_t s);
 hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s);
@@ -180,6 +202,8 @@ hipError_t launch_cgls_advance(int32_t* state, int chunk, hipStream_t s);
 // ring entry k = ||s||^2 of the current column partials, for running problems
 hipError_t launch_cgls_gamma(const CglsArgs& a, int k, hipStream_t s);
 hipError_t launch_cgls_set_base(int32_t* state, int base, hipStream_t s);
+// columns of p a unit can stage (0: no LDS units on this device)
+int32_t lds_unit_capacity(int device);
 hipError_t launch_fill_i32(int32_t* v, int n, int value, hipStream_t s);
 hipError_t launch_fill_f64(double* v, int64_t n, double value, hipStream_t s);
 // one refinement round's start: r64 = b - A c, (p, s) = (0, A^T r), FP64 test
@@ -190,6 +214,9 @@ int64_t segment_blocks(int64_t L);
 // batch construction: dst[i] = src[i] + add (i < count)
 hipError_t launch_copy_add_i32(int32_t* dst, const int32_t* src, int64_t count, int32_t add,
                                hipStream_t s);
+// 16-bit local-column ELL (8 slots) of rows [row0, row0 + nrows) of one problem
+hipError_t launch_ell16(const int32_t* seg_off, const int32_t* perm, int32_t row0, int32_t nrows,
+                        int32_t col_off, uint4* out, hipStream_t s);
 // ELL entries shifted to global columns (col_add) and perm positions (perm_add)
 hipError_t launch_copy_ell(int4* dst, const int4* src, int64_t count, int32_t col_add,
                            int32_t perm_add, hipStream_t s);
@@ -230,6 +257,11 @@ struct fct_plan {
   int32_t* d_row_off = nullptr;    // [K+1]
   int4* d_ell = nullptr;           // [M]
   fct::RowBlock* d_rblk = nullptr; // [nrblk]
+  fct::RowUnit* d_units = nullptr; // [nunits]  FP32 rounds of a batch: LDS units
+  uint4* d_ell16 = nullptr;        // [M]       16-bit ELL of the units' rows
+  fct::RowBlock* d_rblk32 = nullptr; // [nrblk32] FP32 rounds: row blocks outside the units
+  int64_t nunits = 0, nrblk32 = 0;
+  int32_t lds_cap = 0;             // columns a unit stages (floats in LDS)
   fct::ColBlock* d_cblk = nullptr; // [ncblk]
   fct::ProbInfo* d_prob = nullptr; // [nprob]
   double* d_nodes = nullptr;       // [(maxdeg+1) * 64]
@@ -256,7 +288,7 @@ struct fct_ws {
   double* h_gtrue = nullptr;       // pinned [2][nprob]
   double* d_gprev = nullptr;       // [nprob] gamma before the previous round stopped (0: restart)
   double* h_gprev = nullptr;       // pinned [nprob]
-  double* d_part_q = nullptr;      // [nrblk]
+  double* d_part_q = nullptr;      // [4 nrblk] per-wave partials of ||q||^2
   double* d_part_s = nullptr;      // [ncblk]
   double* d_ring = nullptr;        // [nprob][8]
   double* d_gamma0 = nullptr;      // [nprob]

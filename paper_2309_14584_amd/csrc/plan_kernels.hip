@@ -287,7 +287,37 @@ __global__ __launch_bounds__(kBlock) void copy_ell_kernel(int4* __restrict__ dst
   dst[i] = e;
 }
 
+// 16-bit ELL of one problem's rows for the LDS units: the first eight
+// local columns (column - col_off) of each row, 0xFFFF padded; a row with
+// more than eight entries keeps its first seven and marks slot 7 with 0xFFFE
+// (the rest is perm[seg_off[row] + 7, seg_off[row + 1])).
+__global__ __launch_bounds__(kBlock) void ell16_kernel(const int32_t* __restrict__ seg_off,
+                                                       const int32_t* __restrict__ perm,
+                                                       int32_t row0, int32_t nrows,
+                                                       int32_t col_off, uint4* __restrict__ out) {
+  const int32_t i = (int32_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int32_t row = row0 + i;
+  const int32_t t0 = seg_off[row], t1 = seg_off[row + 1];
+  const int32_t len = t1 - t0;
+  uint32_t v[8];
+  for (int k = 0; k < 8; ++k) v[k] = 0xFFFFu;
+  const int32_t direct = len > 8 ? 7 : len;
+  for (int k = 0; k < direct; ++k) v[k] = (uint32_t)(perm[t0 + k] - col_off);
+  if (len > 8) v[7] = 0xFFFEu;
+  out[row] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
+                        v[6] | (v[7] << 16));
+}
+
 }  // namespace
+
+hipError_t launch_ell16(const int32_t* seg_off, const int32_t* perm, int32_t row0, int32_t nrows,
+                        int32_t col_off, uint4* out, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ell16_kernel, dim3((unsigned)ceil_div(nrows, kBlock)), dim3(kBlock), 0, s,
+                     seg_off, perm, row0, nrows, col_off, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_copy_add_i32(int32_t* dst, const int32_t* src, int64_t count, int32_t add,
                                hipStream_t s) {

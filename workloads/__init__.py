@@ -300,17 +300,30 @@ def config3(seed: int = 2, count: int = 256, extra_grids=None):
 
 SERVING_TYPES = ("cfg1_shape", "cfg2_shape", "cfg3_style", "D20_d4")
 
+# The D=20 jobs of the serving mix share one L-grid (and so one resident
+# plan): Alg.-1 grids with degrees U{2..4}, single nodes once the running
+# point count exceeds 4|S|, drawn from a stream of their own.  Their count
+# is the smallest at which the oracle finds the system full rank.
+D20_CAP_MULT = 4
 
-def serving_problem(kind: str, rng_grid, rng_coef) -> Problem:
+
+def d20_grids(seed: int, count: int) -> np.ndarray:
+    """The first ``count`` grids of the D=20 jobs' shared L-grid."""
+    rng = np.random.default_rng([seed, 20])
+    S_n = math.comb(24, 4)                      # |{n in N^20 : |n|_1 <= 4}|
+    return np.array([draw_grid_capped(rng, 20, 2, 4, D20_CAP_MULT * S_n, 0)
+                     for _ in range(count)], dtype=np.int32).reshape(count, 20)
+
+
+def serving_problem(kind: str, rng_grid, rng_coef, d20_count: int = 120) -> Problem:
     """One request of the serving mix.
 
     cfg1_shape: D=2, |n|_1<=16, K=4 grids N_i ~ U{9..24}, planted polynomial.
     cfg2_shape: D=6, |n|_1<=12, grids N_i ~ U{4..8} until 2|S| points and
                 K >= 4, exp-cos with a_i ~ U(0.2,1), w_i ~ U(0.5,2).
     cfg3_style: one problem drawn like the batched workload.
-    D20_d4:     D=20, |n|_1<=4 (10,626 coefficients), Alg.-1 grids (degrees
-                U{1..4}, capped at 4|S| points, single nodes beyond the cap),
-                6D grids to start with, planted.
+    D20_d4:     D=20, |n|_1<=4 (10,626 coefficients) on the shared L-grid
+                (d20_grids, first d20_count grids), planted.
     """
     if kind == "cfg1_shape":
         S = total_degree_support(2, 16)
@@ -329,9 +342,7 @@ def serving_problem(kind: str, rng_grid, rng_coef) -> Problem:
         return p
     if kind == "D20_d4":
         S = total_degree_support(20, 4)
-        grids = np.array([draw_grid_capped(rng_grid, 20, 1, 4, 4 * len(S), 0)
-                          for _ in range(6 * 20)], dtype=np.int32)
-        return Problem(kind, S, grids, FAMILY_PLANTED, np.zeros(0),
+        return Problem(kind, S, None, FAMILY_PLANTED, np.zeros(0),
                        planted_coefficients(rng_coef, S))
     raise ValueError(kind)
 
@@ -344,24 +355,26 @@ def serving_extra_grid(p: Problem, rng):
         return rng.integers(9, 25, size=2)
     if kind == "cfg2_shape":
         return rng.integers(4, 9, size=6)
-    if kind == "D20_d4":
-        return draw_grid_capped(rng, p.D, 1, d, 4 * p.n, 0)
     return draw_grid_capped(rng, p.D, 1, d, p.n, 1)
 
 
-def serving_pool(seed: int = 4, per_type: int = 16, extra_grids=None):
+def serving_pool(seed: int = 4, per_type: int = 16, extra_grids=None, d20_count: int = 120):
     """The serving workload's pool of seeded jobs: per_type jobs of each of
     the four kinds, interleaved (job i has kind SERVING_TYPES[i % 4]).
 
     ``extra_grids`` maps a job index to a number of further grids appended
     to it, drawn by the job's own rule from a stream of its own (job i:
-    default_rng([seed, 1000 + i])): the oracle's Alg.-2 selection stored
-    under tests/golden/."""
+    default_rng([seed, 1000 + i])); ``d20_count`` is the size of the D=20
+    jobs' shared L-grid.  Both come from the oracle's Alg.-2 selection
+    stored under tests/golden/."""
     g_grid, g_coef, _ = streams(seed)
+    shared = d20_grids(seed, d20_count)
     jobs = []
     for i in range(per_type * len(SERVING_TYPES)):
         kind = SERVING_TYPES[i % len(SERVING_TYPES)]
         p = serving_problem(kind, g_grid, g_coef)
+        if kind == "D20_d4":
+            p.grids = shared
         p.name = f"{kind}_{i}"
         p.seed = seed
         jobs.append(p)
