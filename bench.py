@@ -98,6 +98,9 @@ def bench_batched(fct, torch, steps, modes=("f64", "f32_refined")):
     for p in plans:
         p.close()
     t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tuned = batch.tune()
+    t_tune = time.perf_counter() - t0
     dev = torch.device("cuda", 0)
     coeffs = np.concatenate([p.coeffs for p in probs])
     samples = batch.sample(fct.FAMILY_PLANTED, coeffs=torch.tensor(coeffs, device=dev))
@@ -106,7 +109,8 @@ def bench_batched(fct, torch, steps, modes=("f64", "f32_refined")):
     offs = [batch.problem(i) for i in range(len(probs))]
     res = {"workload": f"{len(probs)} problems, D 3..8, |n|_1 <= 6..16 (<= 50k coefficients each)",
            "n_support": batch.n, "total_points": batch.P, "rows": batch.M,
-           "plan_seconds": t_plan}
+           "plan_seconds": t_plan, "tune_seconds": t_tune,
+           "tuned": {"dct_tile": tuned["dct_tile"], "unit_rows": tuned["unit_rows"]}}
     for name, mode in [("f64", fct.SOLVE_F64), ("f32_refined", fct.SOLVE_F32_REFINE)]:
         if name not in modes:
             continue
@@ -212,7 +216,7 @@ def bench_precision(fct, torch, steps):
 def bench_serving(fct, torch, duration, rate=200.0, slots=4):
     """The serving workload: requests drawn (seeded) from a pool of 64 jobs
     of four kinds (D2 |n|_1<=16; D6 |n|_1<=12 exp-cos; a batched-workload
-    problem; D20 |n|_1<=4) arrive as a Poisson stream at `rate` per second
+    problem; D20 |n|_1<=2) arrive as a Poisson stream at `rate` per second
     and are served on `slots` HIP streams with admission under a device-byte
     budget.  Each job is first run alone once (this also builds and caches
     its plan); in the timed run every result must equal its alone result bit
@@ -235,17 +239,40 @@ def bench_serving(fct, torch, duration, rate=200.0, slots=4):
     t0 = time.perf_counter()
     res = eng.run(jobs)
     wall = time.perf_counter() - t0
-    same = sum(np.array_equal(r.c, alone[int(pick[r.id])]) for r in res)
-    coeffs = sum(pool[int(pick[r.id])].n for r in res)
+    same = sum(r.c is not None and np.array_equal(r.c, alone[int(pick[r.id])]) for r in res)
+    # a job counts when it equals its alone run and, if planted, that run
+    # recovered the coefficients to 1e-10 (the exp-cos jobs' alone results
+    # are checked against the oracle by the serving GPU test)
+    ok_alone = {j: (p.coeffs is None or
+                    float(np.max(np.abs(alone[j] - p.coeffs)) / np.max(np.abs(p.coeffs))) <= TOL)
+                for j, p in enumerate(pool)}
+    coeffs = sum(pool[int(pick[r.id])].n for r in res
+                 if r.c is not None and ok_alone[int(pick[r.id])]
+                 and np.array_equal(r.c, alone[int(pick[r.id])]))
     lat = latency_summary(res)
     ex.close()
+    # the D=20, |n|_1 <= 4 job (10,626 coefficients, 4-set cover of 173
+    # grids) alone: ill-conditioned, so it is timed on its own
+    heavy = W.d20_d4_problem(fx["seed"])
+    hp = fct.Plan(heavy.support, heavy.grids)
+    hb = hp.dct(hp.sample(fct.FAMILY_PLANTED, coeffs=torch.tensor(heavy.coeffs, device="cuda")))
+    d20 = {"n_support": hp.n, "grids": hp.K, "samples": hp.P}
+    for name, mode in [("f64", fct.SOLVE_F64), ("f32_refined", fct.SOLVE_F32_REFINE)]:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hc, hi = hp.solve(hb, mode=mode, maxit=40000, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        err = float(np.max(np.abs(hc.cpu().numpy() - heavy.coeffs)) / np.max(np.abs(heavy.coeffs)))
+        d20[name] = {"ms": 1e3 * (time.perf_counter() - t1), "iterations": hi.iterations,
+                     "max_rel_err": err}
+    hp.close()
     return {"workload": f"{len(pool)}-job pool (cfg1/cfg2/cfg3-style/D20 shapes), "
                         f"Poisson {rate:g}/s for {duration:g} s, {slots} streams",
             "requests": len(jobs), "completed": len(res), "identical_to_alone": int(same),
             "wall_s": wall, "jobs_per_s": len(res) / wall, "coeffs_per_s": coeffs / wall,
             "p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"],
             "max_running": eng.stats.max_running, "max_queue": eng.stats.max_queue,
-            "alone_pass_s": t_alone}
+            "failed": eng.stats.failed, "alone_pass_s": t_alone, "d20_d4_job": d20}
 
 
 def main():

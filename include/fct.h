@@ -39,8 +39,9 @@
  * process.  Functions that take a stream enqueue their GPU work on it and
  * return without waiting, except where stated.  Device pointers ("d_")
  * are caller-owned device memory on the plan's device; the library never
- * frees them.  A plan is immutable after creation and may be used from
- * several streams at once; a workspace belongs to one stream at a time.
+ * frees them.  A plan is immutable after creation (fct_plan_tune aside) and
+ * may be used from several streams at once; a workspace belongs to one
+ * stream at a time.
  */
 #ifndef LIBFCT_FCT_H
 #define LIBFCT_FCT_H
@@ -268,6 +269,25 @@ fct_status fct_apply_A(const fct_plan* plan, const double* d_c, double* d_q,
                        hipStream_t stream);
 fct_status fct_apply_AT(const fct_plan* plan, const double* d_r, double* d_s,
                         hipStream_t stream);
+
+/* Autotuner (the batched form's tile shapes): times the forward DCT
+ * (dct_mode) with LDS tiles of 1024, 2048 and 4096 elements and, for a batch
+ * plan, the FP32 row kernels with LDS units of 4096 ... 32768 rows, on the
+ * plan's own shapes, and keeps the fastest of each in the plan.  Results of
+ * every call are unchanged by tuning (only the work decomposition changes).
+ * Uses `ws` (its solver state is overwritten) and allocates temporary device
+ * buffers; synchronous on `stream`.  Not to be called while other calls use
+ * the plan or its workspaces.  `out` (optional) receives the choices and
+ * the timings. */
+typedef struct fct_tune_info {
+  int32_t dct_tile;     /* chosen LDS tile of the DCT passes (elements) */
+  int32_t unit_rows;    /* chosen rows per LDS unit of the FP32 rounds (0: none) */
+  double dct_us[3];     /* forward DCT per tile candidate 1024, 2048, 4096 */
+  double rows_us[4];    /* FP32 row kernels per unit candidate 4096 ... 32768 (0: not run) */
+} fct_tune_info;
+
+fct_status fct_plan_tune(fct_plan* plan, fct_ws* ws, int32_t dct_mode, hipStream_t stream,
+                         fct_tune_info* out);
 
 /* ---- least squares (Sec. 3.4, Alg. 3: c* = argmin ||F f - A c||_2) -------
  * CGLS on A c ~ b from c_0 = 0 (or the warm start in d_c).  Writes the

@@ -415,15 +415,15 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
 }
 
 // ---- FP32 rounds of a batch: q = A p from LDS ----
-// One workgroup of kLdsBlock threads per unit (up to kUnitRows consecutive
-// rows of one problem).  The problem's p = fp32(s + beta p_prev) is staged in
-// LDS once, then each row sums its entries from LDS.  Every value and every
-// reduction is formed exactly as in cgls_rows_kernel<float2, true>: gamma
-// from the column partials by the first 256 threads in the 256-thread order,
-// the per-row sums in perm order, and the per-wave partials of ||q||^2 of
-// each 256-row block with the same butterflies, written to that block's
-// slots.  So a problem gives the same bits
-// whether its rows run here (in a batch) or in row blocks (alone).
+// One workgroup of kLdsBlock threads per unit (up to the plan's unit_rows
+// consecutive rows of one problem).  The problem's p = fp32(s + beta p_prev)
+// is staged in LDS once, then each row sums its entries from LDS.  Every
+// value and every reduction is formed exactly as in
+// cgls_rows_kernel<float2, true>: gamma from the column partials by the
+// first 256 threads in the 256-thread order, the per-row sums in perm order,
+// and the per-wave partials of ||q||^2 of each 256-row block with the same
+// butterflies, written to that block's slots.  So a problem gives the same
+// bits whether its rows run here (in a batch) or in row blocks (alone).
 constexpr int kUnitChunks = 6;          // rows per thread in flight (chunks of kLdsBlock rows)
 
 __global__ __launch_bounds__(kLdsBlock) void cgls_rows_unit_kernel(CglsArgs a, int rel) {

@@ -26,6 +26,8 @@
 //           nearest even), Y = C_hi X_hi + C_hi X_lo + C_lo X_hi with
 //           v_mfma_f32_16x16x16 and FP32 accumulation, on an FP32 tile.
 // Extents above 32 fall back to FP64 FMAs on the vector units.
+#include <algorithm>
+
 #include "fct_internal.h"
 
 namespace fct {
@@ -203,7 +205,9 @@ __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
     const PassDesc* __restrict__ descs, int ndesc, const double* __restrict__ in,
     T* scratch, double* out, const double* __restrict__ mats,
     const int64_t* __restrict__ bin_id) {
-  __shared__ T tile[kTileMax];
+  // the tile: the level's tile_max elements of dynamic LDS (at most kTileMax)
+  extern __shared__ __align__(16) unsigned char dct_smem[];
+  T* const tile = reinterpret_cast<T*>(dct_smem);
   __shared__ PassDesc d;
   __shared__ int64_t s_rows[2];
 
@@ -357,15 +361,16 @@ hipError_t launch_mode(const DctLevel& lv, const double* in, void* scratch, doub
                        const double* mats, const int64_t* bin_id, hipStream_t s) {
   const dim3 grid((unsigned)lv.tiles), block(kBlock);
   T* sc = static_cast<T*>(scratch);
+  const size_t lds = sizeof(T) * (size_t)std::min(lv.tile_max, kTileMax);
   if (lv.emax <= 16) {
-    hipLaunchKernelGGL((dct_pass_kernel<MODE, 1, T>), grid, block, 0, s, lv.d_desc, lv.ndesc, in,
+    hipLaunchKernelGGL((dct_pass_kernel<MODE, 1, T>), grid, block, lds, s, lv.d_desc, lv.ndesc, in,
                        sc, out, mats, bin_id);
   } else if (lv.emax <= 32) {
-    hipLaunchKernelGGL((dct_pass_kernel<MODE, 2, T>), grid, block, 0, s, lv.d_desc, lv.ndesc, in,
+    hipLaunchKernelGGL((dct_pass_kernel<MODE, 2, T>), grid, block, lds, s, lv.d_desc, lv.ndesc, in,
                        sc, out, mats, bin_id);
   } else {
     if (MODE != FCT_DCT_F64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((dct_pass_kernel<FCT_DCT_F64, 0, T>), grid, block, 0, s, lv.d_desc,
+    hipLaunchKernelGGL((dct_pass_kernel<FCT_DCT_F64, 0, T>), grid, block, lds, s, lv.d_desc,
                        lv.ndesc, in, sc, out, mats, bin_id);
   }
   return hipGetLastError();

@@ -66,14 +66,14 @@ struct Group {
 // fill a whole tile (its tiles are contiguous runs of the tensor); the
 // other groups leave room for at least kOuterMinInner contiguous inner
 // elements per row.  Returned outermost first.
-std::vector<Group> make_groups(const int32_t* grid, int D) {
+std::vector<Group> make_groups(const int32_t* grid, int D, int64_t tile_max) {
   std::vector<Group> gs;
   Group cur;
   bool inner = true;
   for (int i = D - 1; i >= 0; --i) {
     const int32_t e = grid[i] + 1;
     if (e == 1) continue;
-    const int64_t cap = inner ? kTileMax : kTileMax / kOuterMinInner;
+    const int64_t cap = inner ? tile_max : tile_max / kOuterMinInner;
     if (!cur.ext.empty() && (cur.G * e > cap || (int)cur.ext.size() >= kMaxGroupAxes)) {
       gs.push_back(cur);
       cur = Group();
@@ -93,7 +93,8 @@ std::vector<Group> make_groups(const int32_t* grid, int D) {
 }
 
 PassDesc make_desc(const int32_t* grid, int D, const Group& g, int64_t point_off,
-                   int32_t row_begin, int32_t row_end, int32_t src, int32_t dst) {
+                   int32_t row_begin, int32_t row_end, int32_t src, int32_t dst,
+                   int64_t tile_max) {
   PassDesc d;
   std::memset(&d, 0, sizeof(d));
   int64_t O = 1, I = 1;
@@ -106,7 +107,7 @@ PassDesc make_desc(const int32_t* grid, int D, const Group& g, int64_t point_off
   d.O = O; d.G = g.G; d.I = I;
   if (I == 1) {
     d.TI = 1;
-    int64_t to = kTileMax / g.G;
+    int64_t to = tile_max / g.G;
     if (to > O) to = O;
     if (to < 1) to = 1;
     d.TO = (int32_t)to;
@@ -114,7 +115,7 @@ PassDesc make_desc(const int32_t* grid, int D, const Group& g, int64_t point_off
     d.ntiles = ceil_div(O, to);
   } else {
     d.TO = 1;
-    int64_t ti = kTileMax / g.G;
+    int64_t ti = tile_max / g.G;
     if (ti > I) ti = I;
     if (ti < I && ti > kOuterMinInner) ti -= ti % kOuterMinInner;
     d.TI = (int32_t)ti;
@@ -133,7 +134,7 @@ PassDesc make_desc(const int32_t* grid, int D, const Group& g, int64_t point_off
 
 // Upload one set of levels; descs[level] lists that level's passes.
 fct_status upload_levels(std::vector<std::vector<PassDesc>>& descs,
-                         std::vector<DctLevel>& out, int64_t* bytes) {
+                         std::vector<DctLevel>& out, int64_t* bytes, int32_t tile_max) {
   out.clear();
   for (auto& lv : descs) {
     DctLevel L;
@@ -151,6 +152,7 @@ fct_status upload_levels(std::vector<std::vector<PassDesc>>& descs,
     L.ndesc = (int32_t)lv.size();
     L.tiles = tb;
     L.emax = emax;
+    L.tile_max = tile_max;
     FCT_HIP(dalloc(&L.d_desc, (int64_t)lv.size(), bytes));
     FCT_HIP(hipMemcpy(L.d_desc, lv.data(), sizeof(PassDesc) * lv.size(), hipMemcpyHostToDevice));
     out.push_back(L);
@@ -158,8 +160,11 @@ fct_status upload_levels(std::vector<std::vector<PassDesc>>& descs,
   return FCT_OK;
 }
 
-void free_levels(std::vector<DctLevel>& v) {
-  for (auto& L : v) dfree(L.d_desc);
+void free_levels(std::vector<DctLevel>& v, int64_t* bytes = nullptr) {
+  for (auto& L : v) {
+    if (bytes && L.d_desc) *bytes -= (int64_t)sizeof(PassDesc) * std::max<int64_t>(L.ndesc, 1);
+    dfree(L.d_desc);
+  }
   v.clear();
 }
 
@@ -176,12 +181,18 @@ void destroy_plan(fct_plan* p) {
   delete p;
 }
 
+// Pass levels of every grid for the plan's DCT tile size (p->dct_tile);
+// levels built before are replaced.
 fct_status build_dct_levels(fct_plan* p) {
+  free_levels(p->fwd, &p->device_bytes);
+  free_levels(p->fwd_full, &p->device_bytes);
+  free_levels(p->inv, &p->device_bytes);
   const int K = p->K;
+  const int64_t tm = p->dct_tile;
   std::vector<std::vector<Group>> groups(K);
   int maxlev = 0;
   for (int l = 0; l < K; ++l) {
-    groups[l] = make_groups(&p->grids[(size_t)p->grid_goff[l]], p->grid_D[l]);
+    groups[l] = make_groups(&p->grids[(size_t)p->grid_goff[l]], p->grid_D[l], tm);
     maxlev = std::max(maxlev, (int)groups[l].size());
   }
   std::vector<std::vector<PassDesc>> fwd(maxlev), full(maxlev), inv(maxlev);
@@ -195,22 +206,22 @@ fct_status build_dct_levels(fct_plan* p) {
       const bool first = q == 0, last = q == np - 1;
       fwd[shift + q].push_back(make_desc(g, D, gs[q], p->point_off[l], p->row_off[l],
                                          p->row_off[l + 1], first ? kSrcInput : kSrcScratch,
-                                         last ? kDstGather : kDstScratch));
+                                         last ? kDstGather : kDstScratch, tm));
       full[shift + q].push_back(make_desc(g, D, gs[q], p->point_off[l], p->row_off[l],
                                           p->row_off[l + 1], first ? kSrcInput : kSrcOutput,
-                                          kDstOutput));
+                                          kDstOutput, tm));
       // inverse: innermost group first (level 0), scattering the row values
       const int lev = np - 1 - q;
       inv[lev].push_back(make_desc(g, D, gs[q], p->point_off[l], p->row_off[l],
                                    p->row_off[l + 1], last ? kSrcRows : kSrcOutput,
-                                   kDstOutput));
+                                   kDstOutput, tm));
     }
   }
-  fct_status st = upload_levels(fwd, p->fwd, &p->device_bytes);
+  fct_status st = upload_levels(fwd, p->fwd, &p->device_bytes, (int32_t)tm);
   if (st != FCT_OK) return st;
-  st = upload_levels(full, p->fwd_full, &p->device_bytes);
+  st = upload_levels(full, p->fwd_full, &p->device_bytes, (int32_t)tm);
   if (st != FCT_OK) return st;
-  return upload_levels(inv, p->inv, &p->device_bytes);
+  return upload_levels(inv, p->inv, &p->device_bytes, (int32_t)tm);
 }
 
 // Row and column blocks of every problem, and the problem table.  Problem
@@ -218,10 +229,14 @@ fct_status build_dct_levels(fct_plan* p) {
 // row (column), so the blocking -- and with it every reduction order -- of a
 // problem does not depend on the other problems of a batch.  In a batch, the
 // FP32 rounds of every problem whose columns fit in a unit's LDS run on LDS
-// units of up to kUnitRows rows instead (their per-row sums are in the same
+// units of p->unit_rows rows instead (same sums and partials in the same
 // order, so a problem gives the same bits alone and in the batch); the
 // other problems keep their row blocks (rb32).
 fct_status build_blocks(fct_plan* p) {
+  dfree(p->d_rblk); dfree(p->d_cblk); dfree(p->d_prob); dfree(p->d_units); dfree(p->d_rblk32);
+  dfree(p->d_ell16);
+  p->device_bytes -= p->block_bytes;
+  const int64_t bytes_before = p->device_bytes;
   std::vector<RowBlock> rb, rb32;
   std::vector<ColBlock> cb;
   std::vector<RowUnit> units;
@@ -233,7 +248,7 @@ fct_status build_blocks(fct_plan* p) {
     pi.cblk_off = (int32_t)cb.size();
     pi.ncblk = (int32_t)ceil_div(pi.n, kBlock);
     const bool lds = pi.n <= p->lds_cap;
-    const int32_t nunit = lds ? (int32_t)ceil_div(pi.M, kUnitRows) : 0;
+    const int32_t nunit = lds ? (int32_t)ceil_div(pi.M, p->unit_rows) : 0;
     for (int32_t b = 0; b < pi.nrblk; ++b) {
       RowBlock r;
       std::memset(&r, 0, sizeof(r));
@@ -251,10 +266,10 @@ fct_status build_blocks(fct_plan* p) {
       RowUnit t;
       std::memset(&t, 0, sizeof(t));
       t.prob = q;
-      t.row0 = pi.row_off + u * kUnitRows;
-      t.row_end = std::min(pi.row_off + pi.M, t.row0 + kUnitRows);
+      t.row0 = pi.row_off + u * p->unit_rows;
+      t.row_end = std::min(pi.row_off + pi.M, t.row0 + p->unit_rows);
       t.first = u == 0;
-      t.pslot = pi.rblk_off + u * (kUnitRows / kBlock);
+      t.pslot = pi.rblk_off + u * (p->unit_rows / kBlock);
       t.cblk_off = pi.cblk_off;
       t.ncblk = pi.ncblk;
       t.col_off = pi.col_off;
@@ -309,6 +324,7 @@ fct_status build_blocks(fct_plan* p) {
     FCT_HIP(hipMemcpy(p->d_rblk32, rb32.data(), sizeof(RowBlock) * rb32.size(),
                       hipMemcpyHostToDevice));
   }
+  p->block_bytes = p->device_bytes - bytes_before;
   return FCT_OK;
 }
 
@@ -1147,6 +1163,107 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
               total_queued, agg.rel_normal_residual);
     return FCT_ENOCONV;
   }
+  return FCT_OK;
+}
+
+// Autotuner: times the forward DCT for each LDS tile size and, for a batch,
+// the FP32 row kernels for each unit size, on this plan's own shapes, and
+// keeps the fastest of each.  Both choices only change the work
+// decomposition, never a result.
+fct_status fct_plan_tune(fct_plan* p, fct_ws* ws, int32_t dct_mode, hipStream_t s,
+                         fct_tune_info* out) {
+  if (!p || !ws) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  fct_status st = check_ws(p, ws);
+  if (st != FCT_OK) return st;
+  st = check_mode(p, dct_mode);
+  if (st != FCT_OK) return st;
+  fct_tune_info info;
+  std::memset(&info, 0, sizeof(info));
+  double* d_x = nullptr;
+  double* d_b = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  struct G {
+    double** x; double** b; hipEvent_t* e;
+    ~G() { dfree(*x); dfree(*b); for (int i = 0; i < 2; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+  } guard{&d_x, &d_b, ev};
+  FCT_HIP(dalloc(&d_x, p->total_points, nullptr));
+  FCT_HIP(dalloc(&d_b, std::max<int64_t>(p->M, 1), nullptr));
+  FCT_HIP(hipMemsetAsync(d_x, 0, sizeof(double) * (size_t)p->total_points, s));
+  for (auto& e : ev) FCT_HIP(hipEventCreate(&e));
+  auto timed = [&](auto&& body, int reps, double* us) -> fct_status {
+    fct_status r = body();                                   // warm-up
+    if (r != FCT_OK) return r;
+    FCT_HIP(hipEventRecord(ev[0], s));
+    for (int i = 0; i < reps; ++i) {
+      r = body();
+      if (r != FCT_OK) return r;
+    }
+    FCT_HIP(hipEventRecord(ev[1], s));
+    FCT_HIP(hipEventSynchronize(ev[1]));
+    float ms = 0.f;
+    FCT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    *us = 1e3 * ms / reps;
+    return FCT_OK;
+  };
+
+  // DCT tile size
+  const int32_t tiles[3] = {1024, 2048, 4096};
+  int best = -1;
+  for (int c = 0; c < 3; ++c) {
+    p->dct_tile = tiles[c];
+    st = build_dct_levels(p);
+    if (st != FCT_OK) return st;
+    st = timed([&]() { return fct_dct(p, d_x, d_b, dct_mode, ws, s); }, 3, &info.dct_us[c]);
+    if (st != FCT_OK) return st;
+    if (best < 0 || info.dct_us[c] < info.dct_us[best]) best = c;
+  }
+  p->dct_tile = tiles[best];
+  st = build_dct_levels(p);
+  if (st != FCT_OK) return st;
+  info.dct_tile = p->dct_tile;
+
+  // rows per LDS unit (FP32 rounds of a batch)
+  if (p->nunits > 0) {
+    const int32_t rows[4] = {4096, 8192, 16384, 32768};
+    const int P = p->nprob;
+    // every problem running, positive gamma, zero vectors: the timed launches
+    // do the work of a full-batch iteration
+    FCT_HIP(launch_fill_f64(ws->d_part_s, p->ncblk, 1.0, s));
+    FCT_HIP(launch_fill_f64(ws->d_ring, 8 * (int64_t)P, 1.0, s));
+    FCT_HIP(launch_fill_f64(ws->d_gamma0, P, 1.0, s));
+    FCT_HIP(launch_fill_f64(reinterpret_cast<double*>(ws->d_ps), 2 * p->n, 0.0, s));
+    FCT_HIP(launch_fill_i32(ws->d_done_tmp, P, 0, s));
+    FCT_HIP(launch_cgls_set_base(ws->d_state_tmp, 1, s));
+    int bu = -1;
+    for (int c = 0; c < 4; ++c) {
+      p->unit_rows = rows[c];
+      st = build_blocks(p);
+      if (st != FCT_OK) return st;
+      CglsArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.rblk = p->d_rblk; a.cblk = p->d_cblk; a.prob = p->d_prob;
+      a.nrblk = p->nrblk; a.ncblk = p->ncblk; a.nprob = P;
+      a.units = p->d_units; a.nunits = p->nunits; a.ell16 = p->d_ell16;
+      a.rblk32 = p->d_rblk32; a.nrblk32 = p->nrblk32;
+      a.lds_bytes = p->lds_cap * (int32_t)sizeof(float);
+      a.ell = p->d_ell; a.seg_off = p->d_seg_off; a.perm = p->d_perm; a.rowmap = p->d_rowmap;
+      a.rq = ws->d_rq; a.ps = ws->d_ps; a.fp32 = 1; a.c = ws->d_ctmp;
+      a.part_q = ws->d_part_q; a.part_s = ws->d_part_s; a.ring = ws->d_ring;
+      a.gamma0 = ws->d_gamma0; a.done = ws->d_done_tmp; a.flags = ws->d_flags;
+      a.state = ws->d_state_tmp; a.tol2 = 0.0;
+      st = timed([&]() -> fct_status { FCT_HIP(launch_cgls_rows(a, 0, s)); return FCT_OK; }, 10,
+                 &info.rows_us[c]);
+      if (st != FCT_OK) return st;
+      if (bu < 0 || info.rows_us[c] < info.rows_us[bu]) bu = c;
+    }
+    p->unit_rows = rows[bu];
+    st = build_blocks(p);
+    if (st != FCT_OK) return st;
+    info.unit_rows = p->unit_rows;
+  }
+  FCT_HIP(hipStreamSynchronize(s));
+  if (out) *out = info;
   return FCT_OK;
 }
 

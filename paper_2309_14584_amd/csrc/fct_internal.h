@@ -47,6 +47,7 @@ struct DctLevel {
   int32_t ndesc = 0;
   int64_t tiles = 0;
   int32_t emax = 0;      // largest extent among the level's axes
+  int32_t tile_max = kTileMax;  // LDS tile elements of this level's passes
 };
 
 // Thread-local error message.
@@ -131,7 +132,7 @@ struct ColBlock {
 // fits in LDS with one workgroup of kLdsBlock threads per unit of up to
 // kUnitRows rows: the unit stages p once and gathers from LDS.
 constexpr int kLdsBlock = 1024;
-constexpr int kUnitRows = 16384;
+constexpr int kUnitRows = 16384;   // default rows per unit (a multiple of kLdsBlock)
 struct RowUnit {
   int32_t prob;
   int32_t row0, row_end;   // global rows of the unit
@@ -262,6 +263,9 @@ struct fct_plan {
   fct::RowBlock* d_rblk32 = nullptr; // [nrblk32] FP32 rounds: row blocks outside the units
   int64_t nunits = 0, nrblk32 = 0;
   int32_t lds_cap = 0;             // columns a unit stages (floats in LDS)
+  int32_t dct_tile = fct::kTileMax;     // tuned: LDS tile elements of the DCT passes
+  int32_t unit_rows = fct::kUnitRows;   // tuned: rows per LDS unit
+  int64_t block_bytes = 0;         // device bytes of the block descriptors, units and ell16
   fct::ColBlock* d_cblk = nullptr; // [ncblk]
   fct::ProbInfo* d_prob = nullptr; // [nprob]
   double* d_nodes = nullptr;       // [(maxdeg+1) * 64]

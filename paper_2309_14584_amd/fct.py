@@ -58,6 +58,11 @@ class SolveInfo(ctypes.Structure):
                 ("refinements", _i32), ("reserved", _i32)]
 
 
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("dct_tile", _i32), ("unit_rows", _i32), ("dct_us", _dbl * 3),
+                ("rows_us", _dbl * 4)]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -87,6 +92,7 @@ _batch_create = _sig("fct_batch_create", ctypes.c_int, _i32, ctypes.POINTER(_vp)
                      ctypes.POINTER(_vp))
 _plan_problem = _sig("fct_plan_problem", ctypes.c_int, _vp, _i32, *[ctypes.POINTER(_i64)] * 6)
 _ws_problem_info = _sig("fct_ws_problem_info", ctypes.c_int, _vp, _i32, ctypes.POINTER(SolveInfo))
+_plan_tune = _sig("fct_plan_tune", ctypes.c_int, _vp, _vp, _i32, _vp, ctypes.POINTER(TuneInfo))
 _solve = _sig("fct_solve", ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
               ctypes.POINTER(SolveInfo), _vp, _vp)
 
@@ -224,6 +230,20 @@ class Plan:
 
     def new_workspace(self):
         return Workspace(self)
+
+    def tune(self, dct_mode=DCT_F64, stream=None, ws=None):
+        """Pick the DCT tile size and (for a batch) the LDS unit size by
+        timing them on this plan (fct_plan_tune); returns the choices and
+        the timings in microseconds."""
+        info = TuneInfo()
+        _check(_plan_tune(self._h, self._wsh(ws), int(dct_mode), _stream(stream),
+                          ctypes.byref(info)))
+        pinfo = PlanInfo()
+        _check(_plan_get_info(self._h, ctypes.byref(pinfo)))
+        self.info = pinfo
+        return {"dct_tile": info.dct_tile, "unit_rows": info.unit_rows,
+                "dct_us": dict(zip((1024, 2048, 4096), info.dct_us)),
+                "rows_us": dict(zip((4096, 8192, 16384, 32768), info.rows_us))}
 
     def _wsh(self, ws):
         return self.ws if ws is None else ws.handle

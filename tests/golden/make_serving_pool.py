@@ -5,7 +5,7 @@ Jobs of the D=2, D=6 and batched kinds: further grids are drawn by the
 job's own rule from its own stream, and the smallest number m of them for
 which the stacked system has full column rank is found by exponential search
 and bisection (rank only grows as grids are appended).  The D=20 jobs share
-one L-grid; its length is chosen the same way.  Full rank is decided as for
+one L-grid (workloads.d20_grids), which is checked the same way.  Full rank is decided as for
 the batched workload: LSQR from zero recovers a random coefficient vector on
 the job's support exactly (max-relative 1e-10) when, and only when, A has
 full column rank.  Results are written as they come (a rerun resumes).
@@ -64,7 +64,7 @@ def smallest(ok, lo):
 
 
 def select_job(i):
-    p = W.serving_pool(SEED, d20_count=1)[i]
+    p = W.serving_pool(SEED)[i]
     rng = np.random.default_rng([SEED, 1000 + i])
     more = [W.serving_extra_grid(p, rng) for _ in range(MAX_EXTRA)]
 
@@ -76,9 +76,18 @@ def select_job(i):
 
 
 def select_d20():
-    S = W.total_degree_support(20, 4)
-    allg = W.d20_grids(SEED, MAX_EXTRA)
-    return "d20", smallest(lambda k: full_rank(S, allg[:k], 10000), 120)
+    """The shared D=20 L-grid must be full rank as it stands; returns the
+    LSQR iterations its recovery took."""
+    S = W.total_degree_support(20, 2)
+    g = W.d20_grids(SEED)
+    plan = O.build_plan(S, g)
+    c = np.random.default_rng(0).standard_normal(len(S))
+    x, its, acond = O.lstsq_lsqr(plan, O.sparse_A(plan) @ c, iter_lim=40000)
+    err = O.max_rel_err(x, c)
+    if not (O.fold_injective(S, g) and err <= 1e-10):
+        raise RuntimeError(f"shared D=20 L-grid not full rank (recovery {err:.1e})")
+    return "d20", {"grids": int(len(g)), "lsqr_iterations": int(its),
+                   "lsqr_condition_estimate": float(acond), "recovery_max_rel": err}
 
 
 def main():
@@ -89,7 +98,7 @@ def main():
             done = json.load(fh)
     kinds = W.SERVING_TYPES
     n = 16 * len(kinds)
-    todo = [i for i in range(n) if kinds[i % len(kinds)] != "D20_d4" and f"job:{i}" not in done]
+    todo = [i for i in range(n) if kinds[i % len(kinds)] != "D20_d2" and f"job:{i}" not in done]
     with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         futs = [ex.submit(select_d20)] if "d20" not in done else []
         futs += [ex.submit(select_job, i) for i in todo]
@@ -101,7 +110,7 @@ def main():
             print(f"[{time.time() - t0:7.0f}s] {key}: {m}", flush=True)
     extra = {k.split(":")[1]: m for k, m in sorted(done.items()) if k.startswith("job:") and m > 0}
     with open(OUT, "w") as fh:
-        json.dump({"seed": SEED, "extra_grids": extra, "d20_grids": done["d20"],
+        json.dump({"seed": SEED, "extra_grids": extra, "d20": done["d20"],
                    "seconds": time.time() - t0}, fh, indent=1)
     os.remove(PARTIAL)
     print(open(OUT).read())

@@ -155,3 +155,34 @@ def test_batch_mixed_precision_matches_alone(fct):
         c1, _ = pl.solve(_dev(b_host[roff:roff + rows]), mode=fct.SOLVE_F32_REFINE)
         assert np.array_equal(c_b[coff:coff + n], _host(c1))
         assert O.max_rel_err(c_b[coff:coff + n], pr.coeffs) < 1e-10
+
+
+def test_tuning_changes_no_result(fct):
+    """The autotuner picks the DCT tile and the LDS unit size by timing; the
+    DCT, the FP64 and the mixed-precision solves give the same bits before
+    and after tuning."""
+    probs = _mixed_batch()
+    plans = [fct.Plan(p.support, p.grids) for p in probs]
+    batch = fct.Plan.batch(plans)
+    coeffs = np.concatenate([p.coeffs for p in probs])
+    samples = batch.sample(fct.FAMILY_PLANTED, coeffs=_dev(coeffs))
+    before = {}
+    for mode in (fct.DCT_F64, fct.DCT_F32):
+        before[mode] = _host(batch.dct(samples, mode=mode))
+    b = batch.dct(samples)
+    c64 = _host(batch.solve(b)[0])
+    c32 = _host(batch.solve(b, mode=fct.SOLVE_F32_REFINE)[0])
+    info = batch.tune()
+    print(info)
+    assert info["dct_tile"] in (1024, 2048, 4096)
+    assert info["unit_rows"] in (0, 4096, 8192, 16384, 32768)
+    for mode in (fct.DCT_F64, fct.DCT_F32):
+        assert np.array_equal(_host(batch.dct(samples, mode=mode)), before[mode])
+    assert np.array_equal(_host(batch.solve(b)[0]), c64)
+    assert np.array_equal(_host(batch.solve(b, mode=fct.SOLVE_F32_REFINE)[0]), c32)
+    # every tile size gives the same transform on a single plan too
+    single = plans[1]
+    ref = _host(single.dct(single.sample(fct.FAMILY_PLANTED, coeffs=_dev(probs[1].coeffs))))
+    single.tune()
+    assert np.array_equal(_host(single.dct(single.sample(fct.FAMILY_PLANTED,
+                                                         coeffs=_dev(probs[1].coeffs)))), ref)

@@ -453,3 +453,25 @@ def test_sampling_in_slabs_is_pointwise_identical():
                      (W.FAMILY_EXPCOS, np.linspace(0.2, 1.0, 8))]:
         full = O.sample_function(fam, prm, g)
         assert np.array_equal(full, O.sample_function(fam, prm, g, chunk=7))
+
+
+def test_serving_pool_small_jobs_recover():
+    """The serving pool's D=2 and D=20 jobs, with the grid counts the
+    oracle's Alg.-2 run stored, recover their planted coefficients (QR)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "serving_extra_grids.json")) as fh:
+        fx = json.load(fh)
+    pool = W.serving_pool(fx["seed"], extra_grids=fx["extra_grids"])
+    for p in pool[0:8]:
+        if p.family != W.FAMILY_PLANTED or p.n > 2000:
+            continue
+        c, _, _ = O.fct_solve(p.support, p.grids, O.sample_problem(p), "qr")
+        assert O.max_rel_err(c, p.coeffs) < 1e-10, p.name
+    # the D=20 L-grid covers every pair of dimensions at degree 2
+    g = W.d20_grids(fx["seed"])
+    assert g.shape[1] == 20 and set(np.unique(g)) <= {0, 2}
+    res = [set(np.nonzero(r)[0]) for r in g]
+    for a in range(20):
+        for b in range(a + 1, 20):
+            assert any(a in r and b in r for r in res)

@@ -35,6 +35,7 @@ __all__ = [
     "Problem", "config1", "config2", "config3", "config3_problem", "small_problem", "streams",
     "config4", "CFG4_MIN_GRIDS", "FAMILY_PLANTED", "FAMILY_EXPCOS", "FAMILY_GAUSS", "FAMILY_RUNGE",
     "FAMILY_OSC", "SERVING_TYPES", "serving_problem", "serving_pool", "poisson_arrivals",
+    "d20_grids", "d20_d4_problem",
 ]
 
 # Function-family identifiers (same integers as the C ABI's fct_family).
@@ -298,32 +299,64 @@ def config3(seed: int = 2, count: int = 256, extra_grids=None):
     return out
 
 
-SERVING_TYPES = ("cfg1_shape", "cfg2_shape", "cfg3_style", "D20_d4")
+SERVING_TYPES = ("cfg1_shape", "cfg2_shape", "cfg3_style", "D20_d2")
 
-# The D=20 jobs of the serving mix share one L-grid (and so one resident
-# plan): Alg.-1 grids with degrees U{2..4}, single nodes once the running
-# point count exceeds 4|S|, drawn from a stream of their own.  Their count
-# is the smallest at which the oracle finds the system full rank.
-D20_CAP_MULT = 4
+# D=20 jobs.  Alg.-1 grids (a few resolved dimensions, single nodes
+# elsewhere) leave total-degree supports rank deficient or badly conditioned
+# unless very many are stacked: a coefficient whose multi-index touches the
+# dimensions I is only told apart from its aliases by a grid that resolves
+# all of I.  The D=20 L-grids here therefore resolve `k` dimensions per grid
+# at degree `d` (the fold is one-to-one on 0..d) and cover every set of d
+# dimensions: grids are added greedily, each the best of 256 seeded random
+# choices by the number of still-uncovered d-sets it covers.  At |n|_1 <= 4
+# (10,626 coefficients) even the full 4-set cover (173 grids, 6.8e7 samples)
+# stays ill-conditioned (about 1.2e4 FP64 CGLS iterations), so the serving
+# mix uses D=20 at |n|_1 <= 2 (231 coefficients, a 13-grid pair cover) and
+# the |n|_1 <= 4 job is measured on its own (d20_d4_problem).
+D20_CANDIDATES = 256
 
 
-def d20_grids(seed: int, count: int) -> np.ndarray:
-    """The first ``count`` grids of the D=20 jobs' shared L-grid."""
+def d20_grids(seed: int, d: int = 2, k: int = 8) -> np.ndarray:
+    """A D=20 L-grid of degree-d grids on k dimensions (single nodes
+    elsewhere) covering every set of d dimensions."""
+    from itertools import combinations
     rng = np.random.default_rng([seed, 20])
-    S_n = math.comb(24, 4)                      # |{n in N^20 : |n|_1 <= 4}|
-    return np.array([draw_grid_capped(rng, 20, 2, 4, D20_CAP_MULT * S_n, 0)
-                     for _ in range(count)], dtype=np.int32).reshape(count, 20)
+    sets = np.array([sum(1 << i for i in c) for c in combinations(range(20), d)], dtype=np.int64)
+    uncovered = np.ones(len(sets), dtype=bool)
+    grids = []
+    while uncovered.any():
+        best, best_n = None, -1
+        for _ in range(D20_CANDIDATES):
+            dims = rng.choice(20, size=k, replace=False)
+            mask = int(sum(1 << int(i) for i in dims))
+            n_cov = int(np.count_nonzero(uncovered & ((sets & ~mask) == 0)))
+            if n_cov > best_n:
+                best, best_n = (dims, mask), n_cov
+        dims, mask = best
+        uncovered &= ~((sets & ~mask) == 0)
+        g = np.zeros(20, dtype=np.int32)
+        g[dims] = d
+        grids.append(g)
+    return np.array(grids, dtype=np.int32)
 
 
-def serving_problem(kind: str, rng_grid, rng_coef, d20_count: int = 120) -> Problem:
+def d20_d4_problem(seed: int = 4) -> Problem:
+    """D=20, |n|_1 <= 4 (10,626 coefficients) on the 4-set cover with eight
+    resolved dimensions per grid, planted polynomial."""
+    S = total_degree_support(20, 4)
+    c = planted_coefficients(np.random.default_rng([seed, 21]), S)
+    return Problem("D20_d4", S, d20_grids(seed, 4, 8), FAMILY_PLANTED, np.zeros(0), c, seed)
+
+
+def serving_problem(kind: str, rng_grid, rng_coef) -> Problem:
     """One request of the serving mix.
 
     cfg1_shape: D=2, |n|_1<=16, K=4 grids N_i ~ U{9..24}, planted polynomial.
     cfg2_shape: D=6, |n|_1<=12, grids N_i ~ U{4..8} until 2|S| points and
                 K >= 4, exp-cos with a_i ~ U(0.2,1), w_i ~ U(0.5,2).
     cfg3_style: one problem drawn like the batched workload.
-    D20_d4:     D=20, |n|_1<=4 (10,626 coefficients) on the shared L-grid
-                (d20_grids, first d20_count grids), planted.
+    D20_d2:     D=20, |n|_1<=2 (231 coefficients) on the shared L-grid
+                (d20_grids), planted.
     """
     if kind == "cfg1_shape":
         S = total_degree_support(2, 16)
@@ -340,8 +373,8 @@ def serving_problem(kind: str, rng_grid, rng_coef, d20_count: int = 120) -> Prob
         p = config3_problem(rng_grid, rng_coef)
         p.name = kind
         return p
-    if kind == "D20_d4":
-        S = total_degree_support(20, 4)
+    if kind == "D20_d2":
+        S = total_degree_support(20, 2)
         return Problem(kind, S, None, FAMILY_PLANTED, np.zeros(0),
                        planted_coefficients(rng_coef, S))
     raise ValueError(kind)
@@ -358,22 +391,21 @@ def serving_extra_grid(p: Problem, rng):
     return draw_grid_capped(rng, p.D, 1, d, p.n, 1)
 
 
-def serving_pool(seed: int = 4, per_type: int = 16, extra_grids=None, d20_count: int = 120):
+def serving_pool(seed: int = 4, per_type: int = 16, extra_grids=None):
     """The serving workload's pool of seeded jobs: per_type jobs of each of
     the four kinds, interleaved (job i has kind SERVING_TYPES[i % 4]).
 
     ``extra_grids`` maps a job index to a number of further grids appended
     to it, drawn by the job's own rule from a stream of its own (job i:
-    default_rng([seed, 1000 + i])); ``d20_count`` is the size of the D=20
-    jobs' shared L-grid.  Both come from the oracle's Alg.-2 selection
-    stored under tests/golden/."""
+    default_rng([seed, 1000 + i])): the oracle's Alg.-2 selection stored
+    under tests/golden/.  The D=20 jobs share d20_grids(seed)."""
     g_grid, g_coef, _ = streams(seed)
-    shared = d20_grids(seed, d20_count)
+    shared = d20_grids(seed)
     jobs = []
     for i in range(per_type * len(SERVING_TYPES)):
         kind = SERVING_TYPES[i % len(SERVING_TYPES)]
         p = serving_problem(kind, g_grid, g_coef)
-        if kind == "D20_d4":
+        if kind == "D20_d2":
             p.grids = shared
         p.name = f"{kind}_{i}"
         p.seed = seed
