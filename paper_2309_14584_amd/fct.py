@@ -100,7 +100,7 @@ EXPORTED = ["fct_last_error", "fct_status_string", "fct_abi_version", "fct_plan_
             "fct_plan_destroy", "fct_plan_get_info", "fct_plan_grid", "fct_plan_export",
             "fct_grid_nodes", "fct_ws_create", "fct_ws_destroy", "fct_sample", "fct_dct",
             "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve", "fct_batch_create",
-            "fct_plan_problem", "fct_ws_problem_info"]
+            "fct_plan_problem", "fct_ws_problem_info", "fct_plan_tune"]
 
 
 class FctError(RuntimeError):
