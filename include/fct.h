@@ -143,6 +143,14 @@ typedef struct fct_solve_opts {
                            (a reliable update) */
   double inner_tol;     /* FCT_SOLVE_F32_REFINE: per-round reduction of the FP32
                            normal residual; 0 selects 1e-5 */
+  int32_t single_kernel; /* 1: for one problem whose row and column blocks each
+                           get a workgroup of their own, run each chunk of
+                           iterations as one cooperative kernel with grid
+                           barriers (same bits as two kernels per iteration;
+                           on MI355X about 6x slower, since every barrier's
+                           agent-scope fences write back and invalidate L2);
+                           0 (default): two kernels per iteration */
+  int32_t reserved2;
 } fct_solve_opts;
 
 typedef struct fct_solve_info {

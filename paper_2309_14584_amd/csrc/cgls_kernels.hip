@@ -243,72 +243,63 @@ __device__ __forceinline__ bool live_problem(const CglsArgs& a, int p) {
 // s <- s - alpha A^T q, so a round can start from s = A^T (b - A c)
 // computed in FP64, which tends to zero at the least-squares solution even
 // when the system is inconsistent (r itself does not).
+//
+// The work of one row block and of one column block is split into a load
+// step (every operand that does not depend on the iteration's scalars,
+// values kept raw so that the loads are all in flight together) and a
+// finish step; the two-kernel iteration and the single-kernel iteration
+// (cgls_fused_kernel) run the same steps, so they give the same bits.
+template <typename P, bool NR> struct RowOps {
+  typedef typename RawOf<P>::type R;
+  R rq_raw, r0, r1, r2, r3;
+  int4 e;
+  int32_t row;
+  bool active;
+};
+
 template <typename P, bool NR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void cgls_rows_kernel(CglsArgs a, int rel) {
-  __shared__ double sh[kShSlots];
-  P* const rqv = static_cast<P*>(a.rq);
-  __shared__ int s_done;
-  const RowBlock bd = a.rblk[blockIdx.x];            // uniform: one scalar load
-  const int p = bd.prob;
-  // the problem's stop flag is read once per workgroup (thread 0, through
-  // LDS), so all of its waves take the same branch even if the problem's
-  // first workgroup sets the flag during this launch
-  if (threadIdx.x == 0) s_done = a.done[p];
-  const int base = a.state[0];
-  // operands that do not depend on this iteration's scalars; in a batch a
-  // problem that has stopped issues none of them
-  const int32_t row = bd.row0 + threadIdx.x;
-  const bool active = row < bd.row_end && live_problem(a, p);
-  // values stay raw (RawOf) until after the barrier, so that the loads are
-  // all in flight together
+__device__ __forceinline__ RowOps<P, NR> rows_load(const CglsArgs& a, const RowBlock& bd,
+                                                   bool live) {
   typedef typename RawOf<P>::type R;
   const R* const rqr = static_cast<const R*>(a.rq);
   const R* const psr = static_cast<const R*>(a.ps);
-  R rq_raw = raw_zero<R>();
-  int4 e = make_int4(-1, -1, -1, -1);
-  if (active) {
-    rq_raw = rqr[row];
-    e = a.ell[row];
+  RowOps<P, NR> o;
+  o.row = bd.row0 + threadIdx.x;
+  o.active = o.row < bd.row_end && live;
+  o.rq_raw = raw_zero<R>();
+  o.e = make_int4(-1, -1, -1, -1);
+  if (o.active) {
+    o.rq_raw = rqr[o.row];
+    o.e = a.ell[o.row];
   }
-  const R r0 = e.x >= 0 ? psr[e.x] : raw_zero<R>();
-  const R r1 = e.y >= 0 ? psr[e.y] : raw_zero<R>();
-  const R r2 = e.z >= 0 ? psr[e.z] : raw_zero<R>();
-  const R r3 = e.w >= 0 ? psr[e.w] : raw_zero<R>();
-  const double gpart = load_partials(a.part_s, bd.cblk_off, bd.ncblk);
-  __syncthreads();
-  if (s_done != 0) return;                           // problem converged or stopped
-  const int k = base + rel;
-  // k0: first iteration of this run (0, or 1 for a mixed-precision round that
-  // continues the previous round's direction; see refine_cols_kernel)
-  const int k0 = a.state[1];
-  double gprev = 1.0, g0 = 0.0, alpha_prev = 0.0;
-  if (k > 0) {
-    gprev = ring_gamma(a.ring, p, k - 1);
-    alpha_prev = ring_alpha(a.ring, p, k - 1);
-    g0 = a.gamma0[p];
-  }
-  const double gamma = block_sum(gpart, sh);
-  const double beta = k > 0 ? gamma / gprev : 0.0;
-  // the first iteration only stops on a zero (or non-finite) normal residual
-  const bool stop = k == k0 ? !(gamma > 0.0) : !(gamma > a.tol2 * g0);
-  if (bd.first && threadIdx.x == 0) {
-    a.ring[p * 8 + (k & 3)] = gamma;
-    if (k == k0) a.gamma0[p] = gamma;
-    if (stop) a.done[p] = k + 1;
-  }
-  if (stop) return;
+  o.r0 = o.e.x >= 0 ? psr[o.e.x] : raw_zero<R>();
+  o.r1 = o.e.y >= 0 ? psr[o.e.y] : raw_zero<R>();
+  o.r2 = o.e.z >= 0 ? psr[o.e.z] : raw_zero<R>();
+  o.r3 = o.e.w >= 0 ? psr[o.e.w] : raw_zero<R>();
+  return o;
+}
+
+// q = A p for the block's rows with p_k = s_k + beta p_{k-1} formed on the
+// fly, r updated, and the per-wave partials of ||q||^2 (no barrier: the
+// consumer adds the four waves of each block in order).
+template <typename P, bool NR>
+__device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& bd,
+                                            const RowOps<P, NR>& o, double beta,
+                                            double alpha_prev) {
+  typedef typename RawOf<P>::type R;
+  const R* const psr = static_cast<const R*>(a.ps);
   double qv = 0.0;
-  if (active) {
-    const double2 rq_old = raw_d2(rq_raw);
-    const double2 v0 = raw_d2(r0), v1 = raw_d2(r1), v2 = raw_d2(r2), v3 = raw_d2(r3);
+  if (o.active) {
+    const int4 e = o.e;
+    const double2 rq_old = raw_d2(o.rq_raw);
+    const double2 v0 = raw_d2(o.r0), v1 = raw_d2(o.r1), v2 = raw_d2(o.r2), v3 = raw_d2(o.r3);
     // terms in perm order: p_k = s_k + beta p_{k-1} for each aliased column
     if (e.x >= 0) qv += direction<P>(beta, v0);
     if (e.y >= 0) qv += direction<P>(beta, v1);
     if (e.z >= 0) qv += direction<P>(beta, v2);
     if (e.w >= 0) qv += direction<P>(beta, v3);
     if (e.w < -1) {                                  // long row: rest of its run in perm
-      const int32_t t1 = a.seg_off[row + 1];
+      const int32_t t1 = a.seg_off[o.row + 1];
       constexpr int kBatch = BatchOf<P>::value;
       for (int32_t t0 = -(e.w + 2); t0 < t1; t0 += kBatch) {
         // kBatch independent index loads, then kBatch independent gathers,
@@ -326,28 +317,81 @@ void cgls_rows_kernel(CglsArgs a, int rel) {
         }
       }
     }
-    if (NR) static_cast<float*>(a.rq)[row] = (float)qv;     // q alone, FP32
-    else rqv[row] = make_pair<P>(fma(-alpha_prev, rq_old.y, rq_old.x), qv);
+    if (NR) static_cast<float*>(a.rq)[o.row] = (float)qv;     // q alone, FP32
+    else static_cast<P*>(a.rq)[o.row] = make_pair<P>(fma(-alpha_prev, rq_old.y, rq_old.x), qv);
   }
-  // per-wave partials of ||q||^2 (no barrier: the consumer adds the four
-  // waves of each block in order)
   const double w = wave_sum(qv * qv);
   if ((threadIdx.x & 63) == 0) a.part_q[4 * (int64_t)bd.pslot + (threadIdx.x >> 6)] = w;
 }
 
+// gamma_k from the column partials, beta, and the stop test of iteration k.
+__device__ __forceinline__ void row_scalars(const CglsArgs& a, int p, int k, double gpart,
+                                            double* sh, double* gamma, double* beta,
+                                            double* alpha_prev, bool* stop) {
+  // k0: first iteration of this run (0, or 1 for a mixed-precision round that
+  // continues the previous round's direction; see refine_cols_kernel)
+  const int k0 = a.state[1];
+  double gprev = 1.0, g0 = 0.0, ap = 0.0;
+  if (k > 0) {
+    gprev = ring_gamma(a.ring, p, k - 1);
+    ap = ring_alpha(a.ring, p, k - 1);
+    g0 = a.gamma0[p];
+  }
+  const double g = block_sum(gpart, sh);
+  *gamma = g;
+  *beta = k > 0 ? g / gprev : 0.0;
+  *alpha_prev = ap;
+  // the first iteration only stops on a zero (or non-finite) normal residual
+  *stop = k == k0 ? !(g > 0.0) : !(g > a.tol2 * g0);
+}
+
+__device__ __forceinline__ void row_scalars_store(const CglsArgs& a, int p, int k, double gamma,
+                                                  bool stop) {
+  a.ring[p * 8 + (k & 3)] = gamma;
+  if (k == a.state[1]) a.gamma0[p] = gamma;
+  if (stop) a.done[p] = k + 1;
+}
+
 template <typename P, bool NR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void cgls_cols_kernel(CglsArgs a, int rel) {
+void cgls_rows_kernel(CglsArgs a, int rel) {
   __shared__ double sh[kShSlots];
-  P* const psv = static_cast<P*>(a.ps);
   __shared__ int s_done;
-  const ColBlock bd = a.cblk[blockIdx.x];
+  const RowBlock bd = a.rblk[blockIdx.x];            // uniform: one scalar load
   const int p = bd.prob;
+  // the problem's stop flag is read once per workgroup (thread 0, through
+  // LDS), so all of its waves take the same branch even if the problem's
+  // first workgroup sets the flag during this launch
   if (threadIdx.x == 0) s_done = a.done[p];
   const int base = a.state[0];
-  const int32_t j = bd.col0 + threadIdx.x;
-  const bool active = j < bd.col_end && live_problem(a, p);
-  const int32_t jl = j - bd.col_off;
+  // operands that do not depend on this iteration's scalars; in a batch a
+  // problem that has stopped issues none of them
+  const RowOps<P, NR> o = rows_load<P, NR>(a, bd, live_problem(a, p));
+  const double gpart = load_partials(a.part_s, bd.cblk_off, bd.ncblk);
+  __syncthreads();
+  if (s_done != 0) return;                           // problem converged or stopped
+  const int k = base + rel;
+  double gamma, beta, alpha_prev;
+  bool stop;
+  row_scalars(a, p, k, gpart, sh, &gamma, &beta, &alpha_prev, &stop);
+  if (bd.first && threadIdx.x == 0) row_scalars_store(a, p, k, gamma, stop);
+  if (stop) return;
+  rows_finish<P, NR>(a, bd, o, beta, alpha_prev);
+}
+
+template <typename P, bool NR> struct ColOps {
+  typedef typename RawOf<P>::type R;
+  typedef typename RowGather<NR, R>::type G;
+  R ps_raw;
+  double c_old;
+  G g[kPrefetch];
+  int32_t j, jl;
+  bool active;
+};
+
+template <typename P, bool NR>
+__device__ __forceinline__ ColOps<P, NR> cols_load(const CglsArgs& a, const ColBlock& bd,
+                                                   bool live) {
   // Unconditional loads from clamped indices (an idle lane reads the
   // block's first column, shared by its whole wave), raw until after the
   // barrier: the index loads and the gathers they feed are each issued
@@ -355,14 +399,76 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
   typedef typename RawOf<P>::type R;
   typedef typename RowGather<NR, R>::type G;
   const G* const rqg = static_cast<const G*>(a.rq);
-  const int32_t jc = active ? j : bd.col0;
+  ColOps<P, NR> o;
+  o.j = bd.col0 + threadIdx.x;
+  o.active = o.j < bd.col_end && live;
+  o.jl = o.j - bd.col_off;
+  const int32_t jc = o.active ? o.j : bd.col0;
   const int32_t jlc = jc - bd.col_off;
-  const R ps_raw = static_cast<const R*>(a.ps)[jc];
-  const double c_old = a.c[jc];
-  G g[kPrefetch];
+  o.ps_raw = static_cast<const R*>(a.ps)[jc];
+  o.c_old = a.c[jc];
 #pragma unroll
   for (int l = 0; l < kPrefetch; ++l)
-    g[l] = rqg[a.rowmap[bd.rmap_off + (l < bd.K ? l : 0) * bd.n + jlc]];
+    o.g[l] = rqg[a.rowmap[bd.rmap_off + (l < bd.K ? l : 0) * bd.n + jlc]];
+  return o;
+}
+
+// p_k stored, c_{k+1} = c_k + alpha p_k, s_{k+1}, and the block's partial of
+// ||s_{k+1}||^2 into part_s[slot].
+template <typename P, bool NR>
+__device__ __forceinline__ void cols_finish(const CglsArgs& a, const ColBlock& bd,
+                                            const ColOps<P, NR>& o, double alpha, double beta,
+                                            double* sh, int64_t slot) {
+  typedef typename RawOf<P>::type R;
+  typedef typename RowGather<NR, R>::type G;
+  const G* const rqg = static_cast<const G*>(a.rq);
+  double sv = 0.0;
+  if (o.active) {
+    const double2 ps_old = raw_d2(o.ps_raw);
+    const double pv = direction<P>(beta, ps_old);
+    a.c[o.j] = fma(alpha, pv, o.c_old);
+    double qs = 0.0;                                 // NR: (A^T q)_j
+#pragma unroll
+    for (int l = 0; l < kPrefetch; ++l) {
+      const double2 v = row_d2(o.g[l]);
+      if (l < bd.K) {
+        if (NR) qs += v.y;
+        else sv += fma(-alpha, v.y, v.x);
+      }
+    }
+    // further grids kBatch at a time: independent loads, sums in grid order
+    constexpr int kBatch = BatchOf<P>::value;
+    for (int l0 = kPrefetch; l0 < bd.K; l0 += kBatch) {
+      G vv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        vv[u] = rqg[a.rowmap[bd.rmap_off + min(l0 + u, bd.K - 1) * bd.n + o.jl]];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const double2 v = row_d2(vv[u]);
+        if (l0 + u < bd.K) {
+          if (NR) qs += v.y;
+          else sv += fma(-alpha, v.y, v.x);
+        }
+      }
+    }
+    if (NR) sv = fma(-alpha, qs, ps_old.y);
+    static_cast<P*>(a.ps)[o.j] = make_pair<P>(pv, sv);
+  }
+  const double part = block_sum(sv * sv, sh);
+  if (threadIdx.x == 0) a.part_s[slot] = part;
+}
+
+template <typename P, bool NR>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void cgls_cols_kernel(CglsArgs a, int rel) {
+  __shared__ double sh[kShSlots];
+  __shared__ int s_done;
+  const ColBlock bd = a.cblk[blockIdx.x];
+  const int p = bd.prob;
+  if (threadIdx.x == 0) s_done = a.done[p];
+  const int base = a.state[0];
+  const ColOps<P, NR> o = cols_load<P, NR>(a, bd, live_problem(a, p));
   const double dpart = load_row_partials(a.part_q, bd.rblk_off, bd.nrblk);
   __syncthreads();
   if (s_done != 0) return;
@@ -377,41 +483,105 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
   }
   const double alpha = gamma / delta;
   if (bd.first && threadIdx.x == 0) a.ring[p * 8 + 4 + (k & 3)] = alpha;
-  double sv = 0.0;
-  if (active) {
-    const double2 ps_old = raw_d2(ps_raw);
-    const double pv = direction<P>(beta, ps_old);
-    a.c[j] = fma(alpha, pv, c_old);
-    double qs = 0.0;                                 // NR: (A^T q)_j
-#pragma unroll
-    for (int l = 0; l < kPrefetch; ++l) {
-      const double2 v = row_d2(g[l]);
-      if (l < bd.K) {
-        if (NR) qs += v.y;
-        else sv += fma(-alpha, v.y, v.x);
-      }
-    }
-    // further grids kBatch at a time: independent loads, sums in grid order
-    constexpr int kBatch = BatchOf<P>::value;
-    for (int l0 = kPrefetch; l0 < bd.K; l0 += kBatch) {
-      G vv[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        vv[u] = rqg[a.rowmap[bd.rmap_off + min(l0 + u, bd.K - 1) * bd.n + jl]];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const double2 v = row_d2(vv[u]);
-        if (l0 + u < bd.K) {
-          if (NR) qs += v.y;
-          else sv += fma(-alpha, v.y, v.x);
+  cols_finish<P, NR>(a, bd, o, alpha, beta, sh, blockIdx.x);
+}
+
+// ---- one problem: the whole iteration in one kernel ----
+// For a single problem small enough that every row block and every column
+// block has a workgroup of its own, cgls_fused_kernel runs `iters`
+// iterations in one launch: row phase, grid barrier, column phase, grid
+// barrier.  Every workgroup forms the iteration's scalars itself from the
+// same partials in the same order (so all agree on when to stop), and the
+// row and column work is exactly that of the two kernels above.
+//
+// The grid barrier needs every workgroup resident (cooperative launch).
+// bar[0] counts arrivals and bar[1] is the generation: a workgroup reads the
+// generation, releases its writes, arrives, and waits for the generation to
+// change; the last arrival resets the count and advances the generation.
+// A wait longer than kSpinLimit polls sets *abort (the host reports a device
+// error) and every later wait returns at once, so no wait is unbounded.
+constexpr long kSpinLimit = 4000000;
+
+__device__ __forceinline__ void grid_sync(int* bar, int nblocks, int* abort) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const int arrived = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
         }
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    if (NR) sv = fma(-alpha, qs, ps_old.y);
-    psv[j] = make_pair<P>(pv, sv);
+    __threadfence();
   }
-  const double part = block_sum(sv * sv, sh);
-  if (threadIdx.x == 0) a.part_s[blockIdx.x] = part;
+  __syncthreads();
+}
+
+template <typename P, bool NR>
+__global__ __launch_bounds__(kBlock) void cgls_fused_kernel(CglsArgs a, int iters, int* bar,
+                                                            int* abort) {
+  __shared__ double sh[kShSlots];
+  __shared__ int s_flag;
+  const int nwg = (int)gridDim.x;
+  const int w = (int)blockIdx.x;
+  const int base = a.state[0];
+  for (int rel = 0; rel < iters; ++rel) {
+    const int k = base + rel;
+    // stopped before (an earlier launch), or a barrier gave up: every
+    // workgroup reads the same values here, after the last barrier
+    if (threadIdx.x == 0)
+      s_flag = __hip_atomic_load(&a.done[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+               __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // row phase
+    RowBlock bd;
+    RowOps<P, NR> o;
+    if (w < a.nrblk) {
+      bd = a.rblk[w];
+      o = rows_load<P, NR>(a, bd, true);
+    }
+    const double gpart = load_partials(a.part_s, 0, (int32_t)a.ncblk);
+    __syncthreads();
+    if (s_flag != 0) break;
+    double gamma, beta, alpha_prev;
+    bool stop;
+    row_scalars(a, 0, k, gpart, sh, &gamma, &beta, &alpha_prev, &stop);
+    if (w == 0 && threadIdx.x == 0) row_scalars_store(a, 0, k, gamma, stop);
+    if (stop) break;
+    for (int64_t b = w; b < a.nrblk; b += nwg) {
+      if (b != w) {
+        bd = a.rblk[b];
+        o = rows_load<P, NR>(a, bd, true);
+      }
+      rows_finish<P, NR>(a, bd, o, beta, alpha_prev);
+    }
+    grid_sync(bar, nwg, abort);
+    // column phase
+    const double dpart = load_row_partials(a.part_q, 0, (int32_t)a.nrblk);
+    const double delta = block_sum(dpart, sh);
+    if (!(delta > 0.0)) {                            // A p = 0: breakdown
+      if (w == 0 && threadIdx.x == 0) { a.flags[0] = 1; a.done[0] = k + 1; }
+      break;
+    }
+    const double alpha = gamma / delta;
+    if (w == 0 && threadIdx.x == 0) a.ring[4 + (k & 3)] = alpha;
+    for (int64_t c = w; c < a.ncblk; c += nwg) {
+      const ColBlock cb = a.cblk[c];
+      const ColOps<P, NR> co = cols_load<P, NR>(a, cb, true);
+      cols_finish<P, NR>(a, cb, co, alpha, beta, sh, c);
+    }
+    grid_sync(bar, nwg, abort);
+  }
 }
 
 // ---- FP32 rounds of a batch: q = A p from LDS ----
@@ -692,6 +862,34 @@ hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s) {
     hipLaunchKernelGGL((cgls_rows_kernel<double2, false>), dim3((unsigned)a.nrblk), dim3(kBlock), 0, s, a, rel);
   }
   return hipGetLastError();
+}
+
+// workgroups of the single-kernel iteration for this plan (0: not possible)
+int32_t fused_grid(int device, int64_t nrblk, int64_t ncblk, int fp32) {
+  int ncu = 0, nb = 0, coop = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess)
+    return 0;
+  const hipError_t e = fp32
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(&cgls_fused_kernel<float2, true>), kBlock, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(&cgls_fused_kernel<double2, false>), kBlock, 0);
+  if (e != hipSuccess || !coop) { (void)hipGetLastError(); return 0; }
+  const int64_t need = std::max(nrblk, ncblk);
+  if (need > (int64_t)nb * ncu) return 0;
+  return (int32_t)need;
+}
+
+hipError_t launch_cgls_fused(const CglsArgs& a, int iters, int32_t grid, int* bar, int* abort,
+                             hipStream_t s) {
+  CglsArgs aa = a;
+  void* args[] = {&aa, &iters, &bar, &abort};
+  if (a.fp32)
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&cgls_fused_kernel<float2, true>),
+                                      dim3((unsigned)grid), dim3(kBlock), args, 0, s);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&cgls_fused_kernel<double2, false>),
+                                    dim3((unsigned)grid), dim3(kBlock), args, 0, s);
 }
 
 int32_t lds_unit_capacity(int device) {

@@ -729,6 +729,8 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   FCT_HIP(dalloc(&w->d_done_tmp, P, nullptr));
   FCT_HIP(dalloc(&w->d_state, 4, nullptr));
   FCT_HIP(dalloc(&w->d_state_tmp, 4, nullptr));
+  FCT_HIP(dalloc(&w->d_bar, 4, nullptr));
+  FCT_HIP(hipMemset(w->d_bar, 0, sizeof(int32_t) * 4));
   FCT_HIP(hipHostMalloc((void**)&w->h_done, sizeof(int32_t) * 3 * P, hipHostMallocDefault));
   FCT_HIP(hipHostMalloc((void**)&w->h_ring, sizeof(double) * 3 * 8 * P, hipHostMallocDefault));
   FCT_HIP(hipHostMalloc((void**)&w->h_gamma0, sizeof(double) * 3 * P, hipHostMallocDefault));
@@ -748,7 +750,7 @@ void fct_ws_destroy(fct_ws* w) {
   dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
   dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_ring); dfree(w->d_gamma0);
   dfree(w->d_done); dfree(w->d_flags); dfree(w->d_done_tmp); dfree(w->d_state);
-  dfree(w->d_state_tmp); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
+  dfree(w->d_state_tmp); dfree(w->d_bar); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
   dfree(w->d_outer);
   if (w->h_outer) (void)hipHostFree(w->h_outer);
   dfree(w->d_gprev);
@@ -893,9 +895,11 @@ static fct_status ensure_graph(fct_ws* ws, const CglsArgs& a, int chunk) {
 // accordingly, so few (early-exiting) launches run after the last problem
 // has converged.  Returns the number of iterations enqueued.
 static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, int k0, int maxit,
-                            int chunk, bool use_graph, hipStream_t s, int* queued_out) {
+                            int chunk, bool use_graph, int32_t fused, hipStream_t s,
+                            int* queued_out) {
   const int P = p->nprob;
   const int g = a.fp32 ? 1 : 0;
+  if (fused > 0) use_graph = false;
   if (use_graph) {
     fct_status st = ensure_graph(ws, a, chunk);
     if (st != FCT_OK) return st;
@@ -909,7 +913,10 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
     while (inflight < 2 && queued < maxit && queued < target) {
       int c = std::min(chunk, std::min(maxit, target) - queued);
       if (c < 1) c = 1;
-      if (use_graph && c == chunk) {
+      if (fused > 0) {
+        FCT_HIP(launch_cgls_fused(a, c, fused, ws->d_bar, ws->d_bar + 2, s));
+        FCT_HIP(launch_cgls_advance(a.state, c, s));
+      } else if (use_graph && c == chunk) {
         FCT_HIP(hipGraphLaunch(ws->graph_exec[g], s));
       } else {
         for (int rel = 0; rel < c; ++rel) FCT_HIP(launch_cgls_iter(a, rel, s));
@@ -1035,6 +1042,15 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   a.r64 = ws->d_r64; a.part_true = ws->d_part_true; a.gtrue0 = ws->d_gtrue;
   a.gtrue = ws->d_gtrue + P; a.outer_done = ws->d_outer;
   const int chunk = o.check_every;
+  // on request, one problem whose blocks each fit a resident workgroup: one
+  // kernel per chunk of iterations (grid barriers between the phases)
+  int32_t fused = 0;
+  if (P == 1 && o.single_kernel > 0) {
+    const int g = mixed ? 1 : 0;
+    if (ws->fused[g] < 0) ws->fused[g] = fused_grid(p->device, p->nrblk, p->ncblk, mixed ? 1 : 0);
+    fused = ws->fused[g];
+  }
+  if (fused > 0) FCT_HIP(launch_fill_i32(ws->d_bar, 4, 0, s));
 
   std::vector<int> iters((size_t)P, 0), rounds((size_t)P, 0);
   int32_t* fd = ws->h_done + (size_t)2 * P;
@@ -1044,7 +1060,7 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   if (!mixed) {
     a.tol2 = o.tol * o.tol;
     FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
-    st = cgls_loop(p, ws, a, 0, o.maxit, chunk, o.use_graph != 0, s, &last_queued);
+    st = cgls_loop(p, ws, a, 0, o.maxit, chunk, o.use_graph != 0, fused, s, &last_queued);
     if (st != FCT_OK) return st;
     total_queued = last_queued;
     FCT_HIP(hipMemcpyAsync(fd, a.done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
@@ -1079,7 +1095,7 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
       for (int q = 0; q < P; ++q) all &= ws->h_outer[q] != 0;
       if (all || round == nround || budget <= 0) break;
       if (o.mode == FCT_SOLVE_F32) a.tol2 = o.tol * o.tol;   // one round to the requested tol
-      st = cgls_loop(p, ws, a, start, budget, chunk, o.use_graph != 0, s, &last_queued);
+      st = cgls_loop(p, ws, a, start, budget, chunk, o.use_graph != 0, fused, s, &last_queued);
       if (st != FCT_OK) return st;
       total_queued += last_queued;
       budget -= last_queued;
@@ -1109,6 +1125,15 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     FCT_HIP(hipStreamSynchronize(s));
   }
 
+  if (fused > 0) {
+    int32_t abort_flag = 0;
+    FCT_HIP(hipMemcpyAsync(&abort_flag, ws->d_bar + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipStreamSynchronize(s));
+    if (abort_flag != 0) {
+      set_error("single-kernel CGLS: a grid barrier waited too long (workgroups not resident?)");
+      return FCT_EDEVICE;
+    }
+  }
   ws->last.assign((size_t)P, fct_solve_info());
   fct_solve_info agg;
   std::memset(&agg, 0, sizeof(agg));

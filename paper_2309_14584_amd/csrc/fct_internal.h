@@ -205,6 +205,10 @@ hipError_t launch_cgls_gamma(const CglsArgs& a, int k, hipStream_t s);
 hipError_t launch_cgls_set_base(int32_t* state, int base, hipStream_t s);
 // columns of p a unit can stage (0: no LDS units on this device)
 int32_t lds_unit_capacity(int device);
+// single-kernel iterations of one problem: workgroups (0: not possible) and launch
+int32_t fused_grid(int device, int64_t nrblk, int64_t ncblk, int fp32);
+hipError_t launch_cgls_fused(const CglsArgs& a, int iters, int32_t grid, int* bar, int* abort,
+                             hipStream_t s);
 hipError_t launch_fill_i32(int32_t* v, int n, int value, hipStream_t s);
 hipError_t launch_fill_f64(double* v, int64_t n, double value, hipStream_t s);
 // one refinement round's start: r64 = b - A c, (p, s) = (0, A^T r), FP64 test
@@ -301,6 +305,8 @@ struct fct_ws {
   int32_t* d_done_tmp = nullptr;   // [nprob] (timing launches)
   int32_t* d_state = nullptr;      // [4]
   int32_t* d_state_tmp = nullptr;  // [4]   (timing launches)
+  int32_t* d_bar = nullptr;        // [4]   grid barrier (count, generation), abort flag
+  int32_t fused[2] = {-1, -1};     // single-kernel workgroups per precision (-1: not yet known)
   // pinned host copies: two in-flight chunk checks, then the final state
   int32_t* h_done = nullptr;       // [3][nprob]
   double* h_ring = nullptr;        // [3][nprob][8]

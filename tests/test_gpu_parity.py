@@ -194,6 +194,25 @@ def test_solve_deterministic_and_graph_matches_eager(fct):
     plan.close()
 
 
+@pytest.mark.parametrize("prob", [W.small_problem(3, 4, 6, 1, 6, 6, W.FAMILY_EXPCOS),
+                                  W.config1(), W.config2()], ids=["expcos_D4", "cfg1", "cfg2"])
+def test_single_kernel_iteration_matches_two_kernels(fct, prob):
+    """A single problem runs each chunk of CGLS iterations as one cooperative
+    kernel with grid barriers; it gives the bits of two kernels per
+    iteration, in FP64 and in the mixed-precision rounds."""
+    plan = fct.Plan(prob.support, prob.grids)
+    coeffs = _dev(prob.coeffs) if prob.coeffs is not None else None
+    b = plan.dct(plan.sample(prob.family, prob.params, coeffs=coeffs))
+    for mode in (fct.SOLVE_F64, fct.SOLVE_F32_REFINE):
+        for chunk in (7, 32):
+            c1, i1 = plan.solve(b, mode=mode, check_every=chunk, single_kernel=True)
+            c1 = _host(c1).copy()
+            c2, i2 = plan.solve(b, mode=mode, check_every=chunk, single_kernel=False)
+            assert i1.iterations == i2.iterations
+            assert np.array_equal(c1, _host(c2))
+    plan.close()
+
+
 def test_solve_warm_start_and_limits(fct):
     prob = W.config1()
     plan = fct.Plan(prob.support, prob.grids)
