@@ -18,7 +18,7 @@ def test_profile_record_parses():
     spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
     b = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(b)
-    for name in ("cgls_cfg2_D6_d12.md", "cgls_batched256.md"):
+    for name in ("cgls_cfg2_D6_d12.md", "cgls_batched256.md", "cgls_cfg4_D12_d10.md"):
         text = open(os.path.join(ROOT, "profiles", name)).read()
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
         assert rec["kernel"].startswith("cgls_rows_kernel<double2")
