@@ -153,9 +153,12 @@ fct_status upload_levels(std::vector<std::vector<PassDesc>>& descs,
     L.tiles = tb;
     L.emax = emax;
     L.tile_max = tile_max;
-    FCT_HIP(dalloc(&L.d_desc, (int64_t)lv.size(), bytes));
-    FCT_HIP(hipMemcpy(L.d_desc, lv.data(), sizeof(PassDesc) * lv.size(), hipMemcpyHostToDevice));
-    out.push_back(L);
+    for (const auto& d : lv) L.rows_io = L.rows_io || d.dst == kDstGather || d.src == kSrcRows;
+    out.push_back(L);   // owned by `out` from here (freed with it on error)
+    DctLevel& R = out.back();
+    FCT_HIP(dalloc(&R.d_desc, (int64_t)lv.size(), bytes));
+    FCT_HIP(hipMemcpy(R.d_desc, lv.data(), sizeof(PassDesc) * lv.size(), hipMemcpyHostToDevice));
+    if (R.rows_io && R.tiles > 0) FCT_HIP(dalloc(&R.d_tile_row, R.tiles, bytes));
   }
   return FCT_OK;
 }
@@ -163,7 +166,9 @@ fct_status upload_levels(std::vector<std::vector<PassDesc>>& descs,
 void free_levels(std::vector<DctLevel>& v, int64_t* bytes = nullptr) {
   for (auto& L : v) {
     if (bytes && L.d_desc) *bytes -= (int64_t)sizeof(PassDesc) * std::max<int64_t>(L.ndesc, 1);
+    if (bytes && L.d_tile_row) *bytes -= (int64_t)sizeof(int32_t) * L.tiles;
     dfree(L.d_desc);
+    dfree(L.d_tile_row);
   }
   v.clear();
 }
@@ -173,8 +178,8 @@ void destroy_plan(fct_plan* p) {
   dfree(p->d_support); dfree(p->d_grids); dfree(p->d_strides); dfree(p->d_point_off);
   dfree(p->d_alias); dfree(p->d_perm); dfree(p->d_seg_off); dfree(p->d_bin_id);
   dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_ell); dfree(p->d_nodes); dfree(p->d_cmat);
-  dfree(p->d_emat); dfree(p->d_rblk); dfree(p->d_cblk); dfree(p->d_prob);
-  dfree(p->d_units); dfree(p->d_rblk32); dfree(p->d_ell16);
+  dfree(p->d_emat); dfree(p->d_cmat32); dfree(p->d_rblk); dfree(p->d_cblk); dfree(p->d_prob);
+  dfree(p->d_units); dfree(p->d_rblk32); dfree(p->d_ell16); dfree(p->d_sdesc);
   free_levels(p->fwd);
   free_levels(p->fwd_full);
   free_levels(p->inv);
@@ -221,7 +226,16 @@ fct_status build_dct_levels(fct_plan* p) {
   if (st != FCT_OK) return st;
   st = upload_levels(full, p->fwd_full, &p->device_bytes, (int32_t)tm);
   if (st != FCT_OK) return st;
-  return upload_levels(inv, p->inv, &p->device_bytes, (int32_t)tm);
+  st = upload_levels(inv, p->inv, &p->device_bytes, (int32_t)tm);
+  if (st != FCT_OK) return st;
+  for (const auto& L : p->fwd) FCT_HIP(launch_tile_rows(L, p->d_bin_id, nullptr));
+  for (const auto& L : p->inv) FCT_HIP(launch_tile_rows(L, p->d_bin_id, nullptr));
+  int cus = 0;
+  FCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
+  for (auto* set : {&p->fwd, &p->fwd_full, &p->inv})
+    for (auto& L : *set) FCT_HIP(dct_level_grids(L, std::max(cus, 1)));
+  FCT_HIP(hipDeviceSynchronize());
+  return FCT_OK;
 }
 
 // Row and column blocks of every problem, and the problem table.  Problem
@@ -332,8 +346,9 @@ fct_status build_tables(fct_plan* p, hipStream_t stream) {
   int64_t* bytes = &p->device_bytes;
   FCT_HIP(dalloc(&p->d_nodes, (int64_t)(p->maxdeg + 1) * 64, bytes));
   FCT_HIP(dalloc(&p->d_cmat, mat_offset(p->maxdeg + 1), bytes));
+  FCT_HIP(dalloc(&p->d_cmat32, mat_offset(p->maxdeg + 1), bytes));
   FCT_HIP(dalloc(&p->d_emat, mat_offset(p->maxdeg + 1), bytes));
-  FCT_HIP(launch_tables(p->maxdeg, p->d_nodes, p->d_cmat, p->d_emat, stream));
+  FCT_HIP(launch_tables(p->maxdeg, p->d_nodes, p->d_cmat, p->d_cmat32, p->d_emat, stream));
   return FCT_OK;
 }
 
@@ -531,6 +546,17 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   if (st != FCT_OK) return st;
   st = build_dct_levels(p);
   if (st != FCT_OK) return st;
+  {
+    std::vector<SampleDesc> sd;
+    make_sample_descs(p->grids, D, K, p->point_off, &sd, &p->sample_tiles);
+    if (p->sample_tiles > 0x7fffffffLL) {
+      set_error("sampling needs %lld workgroups (limit 2^31-1)", (long long)p->sample_tiles);
+      return FCT_EINVAL;
+    }
+    FCT_HIP(dalloc(&p->d_sdesc, (int64_t)sd.size(), bytes));
+    FCT_HIP(hipMemcpy(p->d_sdesc, sd.data(), sizeof(SampleDesc) * sd.size(),
+                      hipMemcpyHostToDevice));
+  }
   guard.p = nullptr;
   *out = p;
   return FCT_OK;
@@ -781,7 +807,8 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
     double* q = reinterpret_cast<double*>(ws->d_rq);   // M doubles of scratch
     FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_coeffs, q, s));
     for (const auto& lv : p->inv)
-      FCT_HIP(launch_dct_level(lv, FCT_DCT_F64, q, nullptr, d_samples, p->d_emat, p->d_bin_id, s));
+      FCT_HIP(launch_dct_level(lv, FCT_DCT_F64, q, nullptr, d_samples, p->d_emat, nullptr,
+                                       p->d_bin_id, s));
     return FCT_OK;
   }
   if (p->nprob != 1) {
@@ -804,7 +831,7 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
   SampleParams prm;
   std::memset(&prm, 0, sizeof(prm));
   for (int i = 0; i < need; ++i) prm.v[i] = params[i];
-  FCT_HIP(launch_sample(family, prm, D, p->K, p->d_grids, p->d_point_off, p->total_points,
+  FCT_HIP(launch_sample(family, prm, D, p->d_sdesc, p->K, p->sample_tiles, p->d_grids,
                         p->d_nodes, d_samples, s));
   return FCT_OK;
 }
@@ -834,7 +861,8 @@ fct_status fct_dct(const fct_plan* p, const double* d_samples, double* d_b, int3
     scratch = ws->d_scratch;
   }
   for (const auto& lv : p->fwd)
-    FCT_HIP(launch_dct_level(lv, mode, d_samples, scratch, d_b, p->d_cmat, p->d_bin_id, s));
+    FCT_HIP(launch_dct_level(lv, mode, d_samples, scratch, d_b, p->d_cmat, p->d_cmat32,
+                                     p->d_bin_id, s));
   return FCT_OK;
 }
 
@@ -846,7 +874,8 @@ fct_status fct_dct_full(const fct_plan* p, const double* d_samples, double* d_ou
   fct_status st = check_mode(p, mode);
   if (st != FCT_OK) return st;
   for (const auto& lv : p->fwd_full)
-    FCT_HIP(launch_dct_level(lv, mode, d_samples, nullptr, d_out, p->d_cmat, p->d_bin_id, s));
+    FCT_HIP(launch_dct_level(lv, mode, d_samples, nullptr, d_out, p->d_cmat, p->d_cmat32,
+                                     p->d_bin_id, s));
   return FCT_OK;
 }
 
@@ -865,11 +894,14 @@ fct_status fct_apply_AT(const fct_plan* p, const double* d_r, double* d_s, hipSt
 }
 
 // Graph of `chunk` CGLS iterations for the given arguments (cached per
-// precision in the workspace; rebuilt when the chunk, d_c or tol change).
+// precision in the workspace; rebuilt when the chunk or any argument
+// changes -- the output, the tolerance, or the plan's block tables, which
+// retuning reallocates).  Callers zero CglsArgs before filling it, so the
+// byte comparison sees no stale padding.
 static fct_status ensure_graph(fct_ws* ws, const CglsArgs& a, int chunk) {
   const int g = a.fp32 ? 1 : 0;
-  if (ws->graph_exec[g] && ws->graph_chunk[g] == chunk && ws->graph_c[g] == a.c &&
-      ws->graph_tol2[g] == a.tol2)
+  if (ws->graph_exec[g] && ws->graph_chunk[g] == chunk &&
+      std::memcmp(&ws->graph_args[g], &a, sizeof(CglsArgs)) == 0)
     return FCT_OK;
   if (ws->graph_exec[g]) { (void)hipGraphExecDestroy(ws->graph_exec[g]); ws->graph_exec[g] = nullptr; }
   hipGraph_t gr = nullptr;
@@ -883,7 +915,8 @@ static fct_status ensure_graph(fct_ws* ws, const CglsArgs& a, int chunk) {
   e = hipGraphInstantiate(&ws->graph_exec[g], gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
   if (e != hipSuccess) { ws->graph_exec[g] = nullptr; return hip_fail(e, "hipGraphInstantiate", __FILE__, __LINE__); }
-  ws->graph_chunk[g] = chunk; ws->graph_c[g] = a.c; ws->graph_tol2[g] = a.tol2;
+  ws->graph_chunk[g] = chunk;
+  ws->graph_args[g] = a;
   return FCT_OK;
 }
 

@@ -48,6 +48,9 @@ struct DctLevel {
   int64_t tiles = 0;
   int32_t emax = 0;      // largest extent among the level's axes
   int32_t tile_max = kTileMax;  // LDS tile elements of this level's passes
+  bool rows_io = false;  // some pass gathers (forward) or scatters (inverse) rows
+  int32_t* d_tile_row = nullptr;  // tiles entries: first row of each such tile
+  int64_t grid[3] = {0, 0, 0};    // persistent workgroups per DCT mode (resident count)
 };
 
 // Thread-local error message.
@@ -79,7 +82,8 @@ hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
                            int64_t n, int32_t* block_counts, int64_t nblocks,
                            int32_t* perm, int32_t* seg_off, int64_t* bin_id,
                            int32_t* rowmap, int32_t* row_off, int K, hipStream_t s);
-hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, double* emat,
+// cmat32: the forward matrices rounded to FP32 (the FP32 DCT mode's operands)
+hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, float* cmat32, double* emat,
                          hipStream_t s);
 // ell[r] = first four entries of row r's run in perm, -1 padded; a row with
 // more than four entries stores -(2 + t) in the last slot, t = perm index
@@ -89,18 +93,39 @@ hipError_t launch_ell(const int32_t* seg_off, const int32_t* perm, int64_t M, in
 
 // DCT passes
 // mode: fct_dct_mode; scratch holds doubles (FP64) or floats (other modes)
+// mats32: FP32 copy of mats (FP32 mode only; may be null otherwise)
 hipError_t launch_dct_level(const DctLevel& lv, int mode, const double* in, void* scratch,
-                            double* out, const double* mats, const int64_t* bin_id,
-                            hipStream_t s);
+                            double* out, const double* mats, const float* mats32,
+                            const int64_t* bin_id, hipStream_t s);
+// fills lv.grid: resident workgroups of each mode's pass kernel (cus: compute units)
+hipError_t dct_level_grids(DctLevel& lv, int cus);
+// fills lv.d_tile_row (allocated by the caller when lv.rows_io)
+hipError_t launch_tile_rows(const DctLevel& lv, const int64_t* bin_id, hipStream_t s);
 
 // sampler: family parameters travel by value in the kernel arguments
 struct SampleParams {
   double v[2 * FCT_MAX_DIM + 2];
 };
-hipError_t launch_sample(int family, const SampleParams& prm, int D, int K,
-                         const int32_t* grids, const int64_t* point_off,
-                         int64_t total_points, const double* nodes, double* out,
-                         hipStream_t s);
+// One sampler workgroup covers R rows of one grid's tensor viewed as
+// O rows x I inner positions (the trailing axes split .. D-1).
+constexpr int kSampleInnerMax = 512;   // inner positions tabulated in LDS
+constexpr int kSampleRowsMax = 256;    // rows per workgroup
+constexpr int kSamplePoints = 8192;    // target points per workgroup
+struct SampleDesc {
+  int64_t point_off;     // offset of the grid's tensor
+  int64_t O;             // rows
+  int64_t tile_begin;    // first workgroup of this grid
+  int32_t grid;          // grid index (degrees at grids + grid * D)
+  int32_t split;         // first inner axis
+  int32_t I;             // inner positions per row (<= kSampleInnerMax, or one axis)
+  int32_t R;             // rows per workgroup (R * I <= max(kSamplePoints, I))
+};
+void make_sample_descs(const std::vector<int32_t>& grids, int D, int K,
+                       const std::vector<int64_t>& point_off, std::vector<SampleDesc>* out,
+                       int64_t* tiles);
+hipError_t launch_sample(int family, const SampleParams& prm, int D, const SampleDesc* descs,
+                         int ndesc, int64_t tiles, const int32_t* grids, const double* nodes,
+                         double* out, hipStream_t s);
 
 // Work decomposition of the CGLS kernels.  A plan holds one or more
 // independent problems (a batch); every workgroup of the row (column)
@@ -255,6 +280,8 @@ struct fct_plan {
   int64_t* d_alias = nullptr;      // [K*n]       (single problem only)
   int32_t* d_grids = nullptr;      // degrees, as `grids`
   int64_t* d_point_off = nullptr;  // [K+1]
+  fct::SampleDesc* d_sdesc = nullptr;  // [K] sampler split of each grid (single problem)
+  int64_t sample_tiles = 0;        // sampler workgroups
   int32_t* d_perm = nullptr;       // [sum K n]   global columns
   int32_t* d_seg_off = nullptr;    // [M+1]       offsets into perm
   int64_t* d_bin_id = nullptr;     // [M]
@@ -274,6 +301,7 @@ struct fct_plan {
   fct::ProbInfo* d_prob = nullptr; // [nprob]
   double* d_nodes = nullptr;       // [(maxdeg+1) * 64]
   double* d_cmat = nullptr;        // packed forward DCT-I matrices, degrees 0..maxdeg
+  float* d_cmat32 = nullptr;       // the same rounded to FP32
   double* d_emat = nullptr;        // packed evaluation matrices
   std::vector<fct::DctLevel> fwd; // forward passes, outer groups first, gather into b
   std::vector<fct::DctLevel> fwd_full; // forward passes writing whole tensors
@@ -316,8 +344,7 @@ struct fct_ws {
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // FP64, FP32 iteration chunks
   hipStream_t graph_stream = nullptr;
   int graph_chunk[2] = {0, 0};
-  double* graph_c[2] = {nullptr, nullptr};
-  double graph_tol2[2] = {-1.0, -1.0};
+  fct::CglsArgs graph_args[2];     // arguments the cached graphs were captured with
   // per-problem results of the last solve
   std::vector<fct_solve_info> last;
 };

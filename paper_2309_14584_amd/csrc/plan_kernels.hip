@@ -222,6 +222,7 @@ __global__ __launch_bounds__(kBlock) void segment_write_kernel(
 // Degree 0 is the 1x1 identity and the single node x = 1.
 __global__ __launch_bounds__(kBlock) void tables_kernel(int maxdeg, double* __restrict__ nodes,
                                                         double* __restrict__ cmat,
+                                                        float* __restrict__ cmat32,
                                                         double* __restrict__ emat) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = mat_offset(maxdeg + 1);
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(kBlock) void tables_kernel(int maxdeg, double* __re
   const int row = (int)(local / e), col = (int)(local % e);
   if (N == 0) {
     cmat[t] = 1.0;
+    cmat32[t] = 1.0f;
     emat[t] = 1.0;
     return;
   }
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(kBlock) void tables_kernel(int maxdeg, double* __re
   const double w = (col == 0 || col == N) ? 1.0 : 2.0;
   const double g = (row == 0 || row == N) ? 0.5 : 1.0;
   cmat[t] = g / (double)N * w * cs;
+  cmat32[t] = (float)cmat[t];
   emat[t] = cs;
 }
 
@@ -389,12 +392,13 @@ hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
   return hipGetLastError();
 }
 
-hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, double* emat, hipStream_t s) {
+hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, float* cmat32, double* emat,
+                         hipStream_t s) {
   int64_t total = mat_offset(maxdeg + 1);
   const int64_t nn = (int64_t)(maxdeg + 1) * 64;
   if (nn > total) total = nn;
   hipLaunchKernelGGL(tables_kernel, dim3((unsigned)ceil_div(total, kBlock)), dim3(kBlock), 0, s,
-                     maxdeg, nodes, cmat, emat);
+                     maxdeg, nodes, cmat, cmat32, emat);
   return hipGetLastError();
 }
 
