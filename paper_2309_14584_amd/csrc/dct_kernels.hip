@@ -212,23 +212,26 @@ __device__ __forceinline__ void axis_vector(T* tile, int nel, int e, int st,
   }
 }
 
-// Extents up to 64 (levels with an axis longer than 16): a runtime loop.
-template <typename T, typename A>
+// Axes longer than 16 (up to EMAX points): the fibre in registers (padded
+// to EMAX, predicated), one output row at a time.
+template <int EMAX, typename T, typename A>
 __device__ __forceinline__ void axis_long(T* tile, int nel, int e, int st,
                                           const A* __restrict__ cm) {
   const int nfib = nel / e;
-  for (int f = threadIdx.x; f < nfib; f += blockDim.x) {
-    const int base = (f / st) * e * st + (f % st);
-    A x[64];
+  const float inv = 1.0f / (float)st;
+  for (int f = threadIdx.x; f < nfib; f += kBlock) {
+    const int hi = div_small(f, st, inv);
+    T* p = tile + (hi * e * st + (f - hi * st));
+    A x[EMAX];
 #pragma unroll
-    for (int k = 0; k < 64; ++k) x[k] = (k < e) ? (A)tile[base + k * st] : (A)0;
+    for (int k = 0; k < EMAX; ++k) x[k] = (k < e) ? (A)p[k * st] : (A)0;
     for (int m = 0; m < e; ++m) {
       const A* row = cm + m * e;
       A acc = 0;
 #pragma unroll
-      for (int k = 0; k < 64; ++k)
+      for (int k = 0; k < EMAX; ++k)
         if (k < e) acc = fma(row[k], x[k], acc);
-      tile[base + m * st] = (T)acc;
+      p[m * st] = (T)acc;
     }
   }
 }
@@ -399,8 +402,9 @@ __device__ __forceinline__ void gather_ahead(const PassDesc& d, const TileGeo& g
 }
 
 // KIND: split-BF16x3 mode: 16-row MFMA blocks of the outputs (1: extents
-// <= 16, 2: <= 32).  FP64 and FP32 modes: 1 = unrolled vector code for
-// extents <= 16, 0 = runtime loop for extents <= 64.
+// <= 16, 2: <= 32).  FP64 and FP32 modes: unrolled vector code for extents
+// <= 16; longer axes (levels of KIND 2: <= 32, KIND 0: <= 64) a loop over
+// output rows with the fibre in registers.
 //
 // PIPE (FP64 tiles): persistent workgroups, as many as are resident, taking
 // tiles blockIdx.x, blockIdx.x + gridDim.x, ...; while a tile is
@@ -480,8 +484,8 @@ __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
     // ---- the next tile: descriptor, and (PIPE) its loads queued ----
     const int64_t tn = tc + step;
     if (tn < tiles) {
-      while (next_begin <= tn) {          // uniform; also skips empty descriptors
-        ++k;
+      if (next_begin <= tn) {             // uniform: the next tile is in a later descriptor
+        k = __builtin_amdgcn_readfirstlane(find_desc(descs, k + 1, ndesc, tn));
         next_begin = k + 1 < ndesc ? descs[k + 1].tile_begin : INT64_MAX;
       }
       nx = tile_geo(descs, k, tn);
@@ -504,8 +508,9 @@ __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
         typedef typename std::conditional<MODE == FCT_DCT_F64, double, float>::type A;
         const A* cm;
         if constexpr (MODE == FCT_DCT_F64) cm = mats + mo; else cm = mats32 + mo;
-        if constexpr (KIND == 1) axis_vector<T, A>(tile, g.nel, e, stride, cm);
-        else axis_long<T, A>(tile, g.nel, e, stride, cm);
+        if (KIND == 1 || e <= 16) axis_vector<T, A>(tile, g.nel, e, stride, cm);
+        else if constexpr (KIND == 2) axis_long<32, T, A>(tile, g.nel, e, stride, cm);
+        else if constexpr (KIND == 0) axis_long<64, T, A>(tile, g.nel, e, stride, cm);
       }
       __syncthreads();
     }
@@ -593,6 +598,7 @@ const void* pass_kernel(int emax) {
     return nullptr;
   } else {
     if (emax <= 16) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 1, T, P>);
+    if (emax <= 32) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 2, T, P>);
     return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 0, T, P>);
   }
 }
@@ -621,6 +627,9 @@ hipError_t launch_mode(const DctLevel& lv, const double* in, void* scratch, doub
   } else {
     if (lv.emax <= 16)
       hipLaunchKernelGGL((dct_pass_kernel<MODE, 1, T, P>), grid, block, lds, s, lv.d_desc,
+                         lv.ndesc, lv.tiles, in, sc, out, mats, mats32, bin_id, tr);
+    else if (lv.emax <= 32)
+      hipLaunchKernelGGL((dct_pass_kernel<MODE, 2, T, P>), grid, block, lds, s, lv.d_desc,
                          lv.ndesc, lv.tiles, in, sc, out, mats, mats32, bin_id, tr);
     else
       hipLaunchKernelGGL((dct_pass_kernel<MODE, 0, T, P>), grid, block, lds, s, lv.d_desc,
