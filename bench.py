@@ -110,7 +110,9 @@ def bench_batched(fct, torch, steps, modes=("f64", "f32_refined")):
     res = {"workload": f"{len(probs)} problems, D 3..8, |n|_1 <= 6..16 (<= 50k coefficients each)",
            "n_support": batch.n, "total_points": batch.P, "rows": batch.M,
            "plan_seconds": t_plan, "tune_seconds": t_tune,
-           "tuned": {"dct_tile": tuned["dct_tile"], "unit_rows": tuned["unit_rows"]}}
+           "tuned": {"dct_tile": tuned["dct_tile"], "unit_rows": tuned["unit_rows"],
+                     "dct_engine": ("vector", "matrix")[tuned["dct_engine"]],
+                     "dct_vector_us": tuned["dct_us"], "dct_matrix_us": tuned["dct_matrix_us"]}}
     for name, mode in [("f64", fct.SOLVE_F64), ("f32_refined", fct.SOLVE_F32_REFINE)]:
         if name not in modes:
             continue
@@ -144,6 +146,31 @@ def bench_batched(fct, torch, steps, modes=("f64", "f32_refined")):
                                  "traffic": measured_traffic("cgls_batched256.md"),
                                  "algorithmic_bytes": algo}
         res[name] = entry
+    if "dct_f32_matrix" in modes:
+        # FP32 DCT on the matrix cores + FP64 solve, at its achieved error
+        # (the FP32 transform's rounding, not the solve, sets the floor)
+        batch.set_dct_engine(fct.DCT_F32, fct.ENGINE_MATRIX)
+
+        def step32():
+            batch.dct(samples, out=b, mode=fct.DCT_F32)
+            return batch.solve(b, out=c, raise_on_noconv=False)[1]
+        step32()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = step32()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        t0 = time.perf_counter()
+        batch.dct(samples, out=b, mode=fct.DCT_F32)
+        torch.cuda.synchronize()
+        t_dct = time.perf_counter() - t0
+        ch = c.cpu().numpy()
+        worst = max(float(np.max(np.abs(ch[coff:coff + n] - p.coeffs)) / np.max(np.abs(p.coeffs)))
+                    for (n, rows, coff, roff, poff, pts), p in zip(offs, probs))
+        res["dct_f32_matrix"] = {"ms_per_step": 1e3 * dt, "dct_ms": 1e3 * t_dct,
+                                 "max_rel_err": worst, "iterations": info.iterations,
+                                 "coeffs_per_s_at_achieved_err": batch.n / dt}
     batch.close()
     return res
 
@@ -187,7 +214,17 @@ def bench_precision(fct, torch, steps):
                          ("dct_bf16x3", fct.DCT_BF16X3)]:
         t_d, _ = timed(lambda: plan.dct(samples, out=b, mode=dmode), steps)
         ent = {"dct_ms": 1e3 * t_d,
-               "dct_grid_samples_per_s": plan.P / t_d}
+               "dct_grid_samples_per_s": plan.P / t_d,
+               "engine": "matrix" if dmode == fct.DCT_BF16X3 else "vector"}
+        if dmode != fct.DCT_BF16X3:
+            # the same contraction on the matrix cores (16x16x4 MFMA), DCT alone
+            b_vec = b.clone()
+            plan.set_dct_engine(dmode, fct.ENGINE_MATRIX)
+            t_m, _ = timed(lambda: plan.dct(samples, out=b, mode=dmode), steps)
+            ent["dct_ms_matrix_engine"] = 1e3 * t_m
+            ent["matrix_vs_vector_max_rel_diff"] = float(
+                ((b - b_vec).abs().max() / b_vec.abs().max()).item())
+            plan.set_dct_engine(dmode, fct.ENGINE_VECTOR)
         for sname, smode in [("f64", fct.SOLVE_F64), ("f32_refined", fct.SOLVE_F32_REFINE)]:
             def step():
                 plan.sample(prob.family, prob.params, out=samples)
@@ -285,7 +322,7 @@ def main():
     ap.add_argument("--skip-batched", action="store_true",
                     help="only the single-problem workload")
     ap.add_argument("--batched-steps", type=int, default=3)
-    ap.add_argument("--batched-modes", default="f64,f32_refined")
+    ap.add_argument("--batched-modes", default="f64,f32_refined,dct_f32_matrix")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-precision", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=3)

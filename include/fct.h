@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FCT_ABI_VERSION 1
+#define FCT_ABI_VERSION 2
 #define FCT_MAX_DIM 64       /* largest D accepted */
 #define FCT_MAX_DEGREE 63    /* largest Lobatto degree N_i (64 nodes) */
 
@@ -77,8 +77,8 @@ typedef enum fct_family {
   FCT_F_OSC = 4      /* sin(3 cos(3 exp|x|^2)) + exp(sin(3 sum_i x_i)) (Sec. 4.3.2, f2) */
 } fct_family;
 
-/* Arithmetic of the DCT contractions (all on the matrix cores for extents
- * up to 32; larger extents use FP64 vector FMAs and accept FCT_DCT_F64 only). */
+/* Arithmetic of the DCT contractions.  FCT_DCT_F32 and FCT_DCT_BF16X3 need
+ * every extent <= 32 (degrees <= 31); FCT_DCT_F64 takes extents up to 64. */
 typedef enum fct_dct_mode {
   FCT_DCT_F64 = 0,    /* FP64 products and sums, FP64 intermediate tensors */
   FCT_DCT_F32 = 1,    /* FP32 products and sums, FP32 intermediate tensors */
@@ -86,6 +86,18 @@ typedef enum fct_dct_mode {
                          even); C_hi x_hi + C_hi x_lo + C_lo x_hi with FP32
                          accumulation; FP32 intermediate tensors */
 } fct_dct_mode;
+
+/* Units that run the FP64 and FP32 DCT contractions of a plan (set with
+ * fct_plan_set_dct_engine or chosen by fct_plan_tune).  The two engines
+ * accumulate in different orders, so their results differ by rounding
+ * within the mode's precision; each is deterministic. */
+typedef enum fct_dct_engine {
+  FCT_ENGINE_VECTOR = 0,  /* E*E multiply-adds per fibre of E points on the
+                             vector units (default for FP64 and FP32) */
+  FCT_ENGINE_MATRIX = 1   /* 16x16x4 MFMA tiles on the matrix cores, 16 fibres
+                             per wave (extents <= 32; the only engine of
+                             FCT_DCT_BF16X3) */
+} fct_dct_engine;
 
 /* Arithmetic of the least-squares solve. */
 typedef enum fct_solve_mode {
@@ -278,20 +290,31 @@ fct_status fct_apply_A(const fct_plan* plan, const double* d_c, double* d_q,
 fct_status fct_apply_AT(const fct_plan* plan, const double* d_r, double* d_s,
                         hipStream_t stream);
 
+/* DCT engine of one mode of a plan (fct_dct_engine).  FCT_EINVAL for an
+ * unknown mode or engine, the vector engine with FCT_DCT_BF16X3, or the
+ * matrix engine on a plan with an extent above 32.  Not to be called while
+ * other calls use the plan. */
+fct_status fct_plan_set_dct_engine(fct_plan* plan, int32_t dct_mode, int32_t engine);
+
 /* Autotuner (the batched form's tile shapes): times the forward DCT
- * (dct_mode) with LDS tiles of 1024, 2048 and 4096 elements and, for a batch
- * plan, the FP32 row kernels with LDS units of 4096 ... 32768 rows, on the
- * plan's own shapes, and keeps the fastest of each in the plan.  Results of
- * every call are unchanged by tuning (only the work decomposition changes).
- * Uses `ws` (its solver state is overwritten) and allocates temporary device
- * buffers; synchronous on `stream`.  Not to be called while other calls use
- * the plan or its workspaces.  `out` (optional) receives the choices and
- * the timings. */
+ * (dct_mode) with LDS tiles of 1024, 2048 and 4096 elements on each engine
+ * the mode allows and, for a batch plan, the FP32 row kernels with LDS units
+ * of 4096 ... 32768 rows, on the plan's own shapes, and keeps the fastest of
+ * each in the plan.  The tile and unit choices leave every result unchanged
+ * (only the work decomposition changes); a change of DCT engine changes the
+ * DCT's rounding (fct_dct_engine).  Uses `ws` (its solver state is
+ * overwritten) and allocates temporary device buffers; synchronous on
+ * `stream`.  Not to be called while other calls use the plan or its
+ * workspaces.  `out` (optional) receives the choices and the timings. */
 typedef struct fct_tune_info {
   int32_t dct_tile;     /* chosen LDS tile of the DCT passes (elements) */
   int32_t unit_rows;    /* chosen rows per LDS unit of the FP32 rounds (0: none) */
-  double dct_us[3];     /* forward DCT per tile candidate 1024, 2048, 4096 */
+  double dct_us[3];     /* forward DCT, vector engine, per tile 1024, 2048, 4096
+                           (0: not run) */
   double rows_us[4];    /* FP32 row kernels per unit candidate 4096 ... 32768 (0: not run) */
+  int32_t dct_engine;   /* chosen engine of dct_mode (fct_dct_engine) */
+  int32_t reserved;
+  double dct_matrix_us[3];  /* forward DCT, matrix engine, per tile (0: not run) */
 } fct_tune_info;
 
 fct_status fct_plan_tune(fct_plan* plan, fct_ws* ws, int32_t dct_mode, hipStream_t stream,

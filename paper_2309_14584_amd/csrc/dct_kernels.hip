@@ -16,19 +16,19 @@
 //
 // One axis of the tile is a batch of small matrix products
 // Y[m, f] = sum_k C[m, k] X[k, f] over its fibres f.  Arithmetic modes:
-//   F64:    FP64 multiply-adds on the vector units, FP64 tile;
-//   F32:    FP32 multiply-adds on the vector units (FP32 matrices), FP32 tile;
-//   BF16X3: on the matrix cores, 16 fibres at a time per wave: the matrix
-//           is the A operand (registers, rows padded to 16 or 32), 16 fibres
-//           the B operand; both split into bf16 high and low parts (round to
-//           nearest even), Y = C_hi X_hi + C_hi X_lo + C_lo X_hi with
-//           v_mfma_f32_16x16x16 and FP32 accumulation, on an FP32 tile.
-// The axes have 2..32 points (mostly 3..8), so a 16x16x4 FP64 or FP32 MFMA
-// tile would be mostly padding while its peak equals the vector units':
-// the FP64 and FP32 contractions run as plain multiply-adds (E*E per fibre
-// of E points); only the bf16 products need the matrix cores.  Every value
-// is computed in place: a thread (wave) reads all of its fibres before it
-// writes any of them, and fibres are disjoint.
+//   F64:    FP64 products and sums, FP64 tile;
+//   F32:    FP32 products and sums (FP32 matrices), FP32 tile;
+//   BF16X3: both operands split into bf16 high and low parts (round to
+//           nearest even), Y = C_hi X_hi + C_hi X_lo + C_lo X_hi with FP32
+//           accumulation, on an FP32 tile (matrix cores only).
+// Two engines run the FP64 and FP32 contractions: the vector units (E*E
+// multiply-adds per fibre of E points) and the matrix cores (16x16x4 MFMA
+// tiles, 16 fibres per wave).  The axes have 2..32 points, mostly 3..8, so
+// an MFMA tile is mostly padding while the FP64 and FP32 MFMA peaks equal
+// the vector units': the vector engine is the default and the plan's
+// tuner times both.  Every value is computed in place: a thread (wave)
+// reads all of its fibres before it writes any of them; fibres are
+// disjoint.
 #include <algorithm>
 #include <climits>
 #include <cstdint>
@@ -38,6 +38,7 @@
 namespace fct {
 namespace {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 
@@ -93,22 +94,68 @@ __device__ __forceinline__ float bf16_to_float(short h) {
   return __uint_as_float(((unsigned)(unsigned short)h) << 16);
 }
 
-// ---- one axis on the matrix cores (split-BF16x3 mode) --------------------
-// MB = 16-row blocks of outputs (e <= 16 * MB).
+// ---- one axis on the matrix cores -----------------------------------------
+// 16 fibres at a time per wave: the matrix is the A operand (registers, rows
+// padded to 16 * MB), 16 fibres the B operand (one LDS load per lane and K
+// step), the result written back in place.  MB = 16-row blocks of outputs
+// (e <= 16 * MB).  FP64: v_mfma_f64_16x16x4; FP32: v_mfma_f32_16x16x4;
+// split-BF16x3: v_mfma_f32_16x16x16bf16 on the bf16 high/low parts.
 template <int MODE, int MB, typename T>
 __device__ __forceinline__ void axis_mfma(T* tile, int nel, int e, int st,
                                           const double* __restrict__ gm) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  static_assert(MODE == FCT_DCT_BF16X3, "FP64 and FP32 axes run on the vector units");
-  constexpr int KS = 16;                // K per MFMA
+  constexpr int KS = (MODE == FCT_DCT_BF16X3) ? 16 : 4;   // K per MFMA
   constexpr int KBMAX = (16 * MB) / KS;
   const int KB = (e + KS - 1) / KS;
   const int nfib = nel / e;
   const int nbatch = (nfib + 15) >> 4;
 
-  {
+  if constexpr (MODE == FCT_DCT_F64 || MODE == FCT_DCT_F32) {
+    typedef typename std::conditional<MODE == FCT_DCT_F64, double, float>::type V;
+    V a[MB][KBMAX];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int kb = 0; kb < KBMAX; ++kb) {
+        const int m = mb * 16 + col, k = kb * 4 + grp;
+        a[mb][kb] = (m < e && k < e) ? (V)gm[m * e + k] : (V)0;
+      }
+    for (int bt = wave; bt < nbatch; bt += nwaves) {
+      const int f = bt * 16 + col;
+      const bool valid = f < nfib;
+      const int base = valid ? (f / st) * e * st + (f % st) : 0;
+      typedef typename std::conditional<MODE == FCT_DCT_F64, v4d, v4f>::type Acc;
+      Acc acc[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = (Acc){0, 0, 0, 0};
+#pragma unroll
+      for (int kb = 0; kb < KBMAX; ++kb) {
+        if (kb < KB) {
+          const int k = kb * 4 + grp;
+          const V bv = (valid && k < e) ? (V)tile[base + k * st] : (V)0;
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            if constexpr (MODE == FCT_DCT_F64)
+              acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][kb], bv, acc[mb], 0, 0, 0);
+            else
+              acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][kb], bv, acc[mb], 0, 0, 0);
+          }
+        }
+      }
+      if (valid) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            // f64 tiles: lane holds rows grp + 4r; f32 tiles: rows 4 grp + r
+            const int m = mb * 16 + (MODE == FCT_DCT_F64 ? grp + 4 * r : 4 * grp + r);
+            if (m < e) tile[base + m * st] = (T)acc[mb][r];
+          }
+      }
+    }
+  } else {
     v4s ah[MB][KBMAX], al[MB][KBMAX];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -401,10 +448,10 @@ __device__ __forceinline__ void gather_ahead(const PassDesc& d, const TileGeo& g
   }
 }
 
-// KIND: split-BF16x3 mode: 16-row MFMA blocks of the outputs (1: extents
-// <= 16, 2: <= 32).  FP64 and FP32 modes: unrolled vector code for extents
-// <= 16; longer axes (levels of KIND 2: <= 32, KIND 0: <= 64) a loop over
-// output rows with the fibre in registers.
+// MF (matrix cores; split-BF16x3 always): KIND = 16-row MFMA blocks of the
+// outputs (1: extents <= 16, 2: <= 32).  Vector units (FP64, FP32):
+// unrolled code for extents <= 16; longer axes (levels of KIND 2: <= 32,
+// KIND 0: <= 64) a loop over output rows with the fibre in registers.
 //
 // PIPE (FP64 tiles): persistent workgroups, as many as are resident, taking
 // tiles blockIdx.x, blockIdx.x + gridDim.x, ...; while a tile is
@@ -412,7 +459,7 @@ __device__ __forceinline__ void gather_ahead(const PassDesc& d, const TileGeo& g
 // next tile (and the offsets of the rows it gathers) are already in flight
 // in registers.  Without PIPE (FP32 tiles, half the bytes) one workgroup
 // per tile, with fewer registers and so more workgroups resident.
-template <int MODE, int KIND, typename T, bool PIPE>
+template <int MODE, int KIND, typename T, bool PIPE, bool MF>
 __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
     const PassDesc* __restrict__ descs, int ndesc, int64_t tiles,
     const double* __restrict__ in, T* scratch, double* out, const double* __restrict__ mats,
@@ -502,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void dct_pass_kernel(
       const int e = __builtin_amdgcn_readfirstlane(d.ext[a]);
       stride /= e;                        // stride of axis a inside the tile
       const int64_t mo = mat_offset(e - 1);
-      if constexpr (MODE == FCT_DCT_BF16X3) {
+      if constexpr (MF) {
         axis_mfma<MODE, KIND, T>(tile, g.nel, e, stride, mats + mo);
       } else {
         typedef typename std::conditional<MODE == FCT_DCT_F64, double, float>::type A;
@@ -586,78 +633,67 @@ __global__ __launch_bounds__(kBlock) void tile_rows_kernel(
 }
 
 // FP64 tiles run persistent and pipelined; FP32 tiles one per workgroup.
-template <int MODE, typename T>
+template <typename T>
 constexpr bool kPipe = sizeof(T) == 8;
 
-template <int MODE, typename T>
+// The pass kernel of a level for a mode and engine (null: not available).
+template <int MODE, typename T, bool MF>
 const void* pass_kernel(int emax) {
-  constexpr bool P = kPipe<MODE, T>;
-  if constexpr (MODE == FCT_DCT_BF16X3) {
-    if (emax <= 16) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 1, T, P>);
-    if (emax <= 32) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 2, T, P>);
+  constexpr bool P = kPipe<T>;
+  if constexpr (MF) {
+    if (emax <= 16) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 1, T, P, true>);
+    if (emax <= 32) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 2, T, P, true>);
     return nullptr;
   } else {
-    if (emax <= 16) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 1, T, P>);
-    if (emax <= 32) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 2, T, P>);
-    return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 0, T, P>);
+    if (emax <= 16) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 1, T, P, false>);
+    if (emax <= 32) return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 2, T, P, false>);
+    return reinterpret_cast<const void*>(&dct_pass_kernel<MODE, 0, T, P, false>);
   }
 }
 
-template <int MODE, typename T>
+template <int MODE, typename T, bool MF>
 hipError_t launch_mode(const DctLevel& lv, const double* in, void* scratch, double* out,
                        const double* mats, const float* mats32, const int64_t* bin_id,
                        hipStream_t s) {
-  constexpr bool P = kPipe<MODE, T>;
-  const int64_t nwg = P ? std::min<int64_t>(lv.tiles, lv.grid[MODE]) : lv.tiles;
+  constexpr bool P = kPipe<T>;
+  const void* f = pass_kernel<MODE, T, MF>(lv.emax);
+  if (!f) return hipErrorInvalidValue;
+  const int64_t nwg = P ? std::min<int64_t>(lv.tiles, lv.grid[MODE][MF ? 1 : 0]) : lv.tiles;
   if (nwg <= 0 || nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)nwg), block(kBlock);
-  T* sc = static_cast<T*>(scratch);
-  const size_t lds = sizeof(T) * (size_t)std::min(lv.tile_max, kTileMax);
-  const int32_t* tr = lv.d_tile_row;
   if (MODE == FCT_DCT_F32 && !mats32) return hipErrorInvalidValue;
-  if constexpr (MODE == FCT_DCT_BF16X3) {
-    if (lv.emax <= 16)
-      hipLaunchKernelGGL((dct_pass_kernel<MODE, 1, T, P>), grid, block, lds, s, lv.d_desc,
-                         lv.ndesc, lv.tiles, in, sc, out, mats, mats32, bin_id, tr);
-    else if (lv.emax <= 32)
-      hipLaunchKernelGGL((dct_pass_kernel<MODE, 2, T, P>), grid, block, lds, s, lv.d_desc,
-                         lv.ndesc, lv.tiles, in, sc, out, mats, mats32, bin_id, tr);
-    else
-      return hipErrorInvalidValue;
-  } else {
-    if (lv.emax <= 16)
-      hipLaunchKernelGGL((dct_pass_kernel<MODE, 1, T, P>), grid, block, lds, s, lv.d_desc,
-                         lv.ndesc, lv.tiles, in, sc, out, mats, mats32, bin_id, tr);
-    else if (lv.emax <= 32)
-      hipLaunchKernelGGL((dct_pass_kernel<MODE, 2, T, P>), grid, block, lds, s, lv.d_desc,
-                         lv.ndesc, lv.tiles, in, sc, out, mats, mats32, bin_id, tr);
-    else
-      hipLaunchKernelGGL((dct_pass_kernel<MODE, 0, T, P>), grid, block, lds, s, lv.d_desc,
-                         lv.ndesc, lv.tiles, in, sc, out, mats, mats32, bin_id, tr);
-  }
-  return hipGetLastError();
+  T* sc = static_cast<T*>(scratch);
+  const PassDesc* descs = lv.d_desc;
+  int ndesc = lv.ndesc;
+  int64_t tiles = lv.tiles;
+  const int32_t* tr = lv.d_tile_row;
+  void* args[] = {&descs, &ndesc, &tiles, &in, &sc, &out, &mats, &mats32, &bin_id, &tr};
+  const size_t lds = sizeof(T) * (size_t)std::min(lv.tile_max, kTileMax);
+  return hipLaunchKernel(f, dim3((unsigned)nwg), dim3(kBlock), args, lds, s);
 }
 
-// Resident workgroups of one mode's pass kernel on the device: the
-// persistent grid of a level (at least one workgroup per compute unit).
-template <int MODE, typename T>
+// Resident workgroups of one mode's and engine's pass kernel on the device:
+// the persistent grid of a level (at least one workgroup per compute unit).
+template <int MODE, typename T, bool MF>
 hipError_t resident_grid(DctLevel& lv, int cus) {
-  const void* f = pass_kernel<MODE, T>(lv.emax);
-  if (!f) { lv.grid[MODE] = 0; return hipSuccess; }
+  const void* f = pass_kernel<MODE, T, MF>(lv.emax);
+  int64_t& g = lv.grid[MODE][MF ? 1 : 0];
+  if (!f) { g = 0; return hipSuccess; }
   const size_t lds = sizeof(T) * (size_t)std::min(lv.tile_max, kTileMax);
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, lds);
   if (e != hipSuccess) return e;
-  lv.grid[MODE] = (int64_t)std::max(per_cu, 1) * cus;
+  g = (int64_t)std::max(per_cu, 1) * cus;
   return hipSuccess;
 }
 
 }  // namespace
 
 hipError_t dct_level_grids(DctLevel& lv, int cus) {
-  hipError_t e = resident_grid<FCT_DCT_F64, double>(lv, cus);
-  if (e == hipSuccess) e = resident_grid<FCT_DCT_F32, float>(lv, cus);
-  if (e == hipSuccess) e = resident_grid<FCT_DCT_BF16X3, float>(lv, cus);
+  hipError_t e = resident_grid<FCT_DCT_F64, double, false>(lv, cus);
+  if (e == hipSuccess) e = resident_grid<FCT_DCT_F64, double, true>(lv, cus);
+  if (e == hipSuccess) e = resident_grid<FCT_DCT_F32, float, false>(lv, cus);
+  if (e == hipSuccess) e = resident_grid<FCT_DCT_F32, float, true>(lv, cus);
+  if (e == hipSuccess) e = resident_grid<FCT_DCT_BF16X3, float, true>(lv, cus);
   return e;
 }
 
@@ -669,18 +705,27 @@ hipError_t launch_tile_rows(const DctLevel& lv, const int64_t* bin_id, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_dct_level(const DctLevel& lv, int mode, const double* in, void* scratch,
-                            double* out, const double* mats, const float* mats32,
+hipError_t launch_dct_level(const DctLevel& lv, int mode, int engine, const double* in,
+                            void* scratch, double* out, const double* mats, const float* mats32,
                             const int64_t* bin_id, hipStream_t s) {
   if (lv.tiles == 0) return hipSuccess;
   if (lv.rows_io && !lv.d_tile_row) return hipErrorInvalidValue;
+  const bool mf = engine == FCT_ENGINE_MATRIX;
   switch (mode) {
     case FCT_DCT_F64:
-      return launch_mode<FCT_DCT_F64, double>(lv, in, scratch, out, mats, mats32, bin_id, s);
+      return mf ? launch_mode<FCT_DCT_F64, double, true>(lv, in, scratch, out, mats, mats32,
+                                                           bin_id, s)
+                : launch_mode<FCT_DCT_F64, double, false>(lv, in, scratch, out, mats, mats32,
+                                                            bin_id, s);
     case FCT_DCT_F32:
-      return launch_mode<FCT_DCT_F32, float>(lv, in, scratch, out, mats, mats32, bin_id, s);
+      return mf ? launch_mode<FCT_DCT_F32, float, true>(lv, in, scratch, out, mats, mats32,
+                                                          bin_id, s)
+                : launch_mode<FCT_DCT_F32, float, false>(lv, in, scratch, out, mats, mats32,
+                                                           bin_id, s);
     case FCT_DCT_BF16X3:
-      return launch_mode<FCT_DCT_BF16X3, float>(lv, in, scratch, out, mats, mats32, bin_id, s);
+      if (!mf) return hipErrorInvalidValue;
+      return launch_mode<FCT_DCT_BF16X3, float, true>(lv, in, scratch, out, mats, mats32, bin_id,
+                                                       s);
     default: return hipErrorInvalidValue;
   }
 }

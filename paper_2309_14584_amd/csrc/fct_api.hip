@@ -807,8 +807,8 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
     double* q = reinterpret_cast<double*>(ws->d_rq);   // M doubles of scratch
     FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_coeffs, q, s));
     for (const auto& lv : p->inv)
-      FCT_HIP(launch_dct_level(lv, FCT_DCT_F64, q, nullptr, d_samples, p->d_emat, nullptr,
-                                       p->d_bin_id, s));
+      FCT_HIP(launch_dct_level(lv, FCT_DCT_F64, FCT_ENGINE_VECTOR, q, nullptr, d_samples,
+                                       p->d_emat, nullptr, p->d_bin_id, s));
     return FCT_OK;
   }
   if (p->nprob != 1) {
@@ -861,8 +861,8 @@ fct_status fct_dct(const fct_plan* p, const double* d_samples, double* d_b, int3
     scratch = ws->d_scratch;
   }
   for (const auto& lv : p->fwd)
-    FCT_HIP(launch_dct_level(lv, mode, d_samples, scratch, d_b, p->d_cmat, p->d_cmat32,
-                                     p->d_bin_id, s));
+    FCT_HIP(launch_dct_level(lv, mode, p->dct_engine[mode], d_samples, scratch, d_b,
+                                     p->d_cmat, p->d_cmat32, p->d_bin_id, s));
   return FCT_OK;
 }
 
@@ -874,8 +874,8 @@ fct_status fct_dct_full(const fct_plan* p, const double* d_samples, double* d_ou
   fct_status st = check_mode(p, mode);
   if (st != FCT_OK) return st;
   for (const auto& lv : p->fwd_full)
-    FCT_HIP(launch_dct_level(lv, mode, d_samples, nullptr, d_out, p->d_cmat, p->d_cmat32,
-                                     p->d_bin_id, s));
+    FCT_HIP(launch_dct_level(lv, mode, p->dct_engine[mode], d_samples, nullptr, d_out,
+                                     p->d_cmat, p->d_cmat32, p->d_bin_id, s));
   return FCT_OK;
 }
 
@@ -1265,21 +1265,31 @@ fct_status fct_plan_tune(fct_plan* p, fct_ws* ws, int32_t dct_mode, hipStream_t 
     return FCT_OK;
   };
 
-  // DCT tile size
+  // DCT tile size and engine
   const int32_t tiles[3] = {1024, 2048, 4096};
-  int best = -1;
+  const bool vec_ok = dct_mode != FCT_DCT_BF16X3;
+  const bool mat_ok = p->maxdeg <= 31;
+  int best_tile = -1, best_engine = -1;
+  double best_us = 0.0;
   for (int c = 0; c < 3; ++c) {
     p->dct_tile = tiles[c];
     st = build_dct_levels(p);
     if (st != FCT_OK) return st;
-    st = timed([&]() { return fct_dct(p, d_x, d_b, dct_mode, ws, s); }, 3, &info.dct_us[c]);
-    if (st != FCT_OK) return st;
-    if (best < 0 || info.dct_us[c] < info.dct_us[best]) best = c;
+    for (int eng = FCT_ENGINE_VECTOR; eng <= FCT_ENGINE_MATRIX; ++eng) {
+      if ((eng == FCT_ENGINE_VECTOR && !vec_ok) || (eng == FCT_ENGINE_MATRIX && !mat_ok)) continue;
+      p->dct_engine[dct_mode] = eng;
+      double* slot = eng == FCT_ENGINE_VECTOR ? &info.dct_us[c] : &info.dct_matrix_us[c];
+      st = timed([&]() { return fct_dct(p, d_x, d_b, dct_mode, ws, s); }, 3, slot);
+      if (st != FCT_OK) return st;
+      if (best_tile < 0 || *slot < best_us) { best_tile = c; best_engine = eng; best_us = *slot; }
+    }
   }
-  p->dct_tile = tiles[best];
+  p->dct_tile = tiles[best_tile];
+  p->dct_engine[dct_mode] = best_engine;
   st = build_dct_levels(p);
   if (st != FCT_OK) return st;
   info.dct_tile = p->dct_tile;
+  info.dct_engine = best_engine;
 
   // rows per LDS unit (FP32 rounds of a batch)
   if (p->nunits > 0) {
@@ -1322,6 +1332,28 @@ fct_status fct_plan_tune(fct_plan* p, fct_ws* ws, int32_t dct_mode, hipStream_t 
   }
   FCT_HIP(hipStreamSynchronize(s));
   if (out) *out = info;
+  return FCT_OK;
+}
+
+fct_status fct_plan_set_dct_engine(fct_plan* p, int32_t dct_mode, int32_t engine) {
+  if (!p) { set_error("NULL plan"); return FCT_EINVAL; }
+  if (dct_mode < FCT_DCT_F64 || dct_mode > FCT_DCT_BF16X3) {
+    set_error("unknown DCT mode %d", dct_mode);
+    return FCT_EINVAL;
+  }
+  if (engine != FCT_ENGINE_VECTOR && engine != FCT_ENGINE_MATRIX) {
+    set_error("unknown DCT engine %d", engine);
+    return FCT_EINVAL;
+  }
+  if (engine == FCT_ENGINE_VECTOR && dct_mode == FCT_DCT_BF16X3) {
+    set_error("the split-BF16x3 DCT runs on the matrix cores only");
+    return FCT_EINVAL;
+  }
+  if (engine == FCT_ENGINE_MATRIX && p->maxdeg > 31) {
+    set_error("the matrix engine needs every degree <= 31 (plan has %d)", p->maxdeg);
+    return FCT_EINVAL;
+  }
+  p->dct_engine[dct_mode] = engine;
   return FCT_OK;
 }
 

@@ -50,7 +50,7 @@ struct DctLevel {
   int32_t tile_max = kTileMax;  // LDS tile elements of this level's passes
   bool rows_io = false;  // some pass gathers (forward) or scatters (inverse) rows
   int32_t* d_tile_row = nullptr;  // tiles entries: first row of each such tile
-  int64_t grid[3] = {0, 0, 0};    // persistent workgroups per DCT mode (resident count)
+  int64_t grid[3][2] = {};        // persistent workgroups per DCT mode and engine
 };
 
 // Thread-local error message.
@@ -93,9 +93,10 @@ hipError_t launch_ell(const int32_t* seg_off, const int32_t* perm, int64_t M, in
 
 // DCT passes
 // mode: fct_dct_mode; scratch holds doubles (FP64) or floats (other modes)
-// mats32: FP32 copy of mats (FP32 mode only; may be null otherwise)
-hipError_t launch_dct_level(const DctLevel& lv, int mode, const double* in, void* scratch,
-                            double* out, const double* mats, const float* mats32,
+// engine: fct_dct_engine; mats32: FP32 copy of mats (FP32 mode only; may be
+// null otherwise)
+hipError_t launch_dct_level(const DctLevel& lv, int mode, int engine, const double* in,
+                            void* scratch, double* out, const double* mats, const float* mats32,
                             const int64_t* bin_id, hipStream_t s);
 // fills lv.grid: resident workgroups of each mode's pass kernel (cus: compute units)
 hipError_t dct_level_grids(DctLevel& lv, int cus);
@@ -295,6 +296,7 @@ struct fct_plan {
   int64_t nunits = 0, nrblk32 = 0;
   int32_t lds_cap = 0;             // columns a unit stages (floats in LDS)
   int32_t dct_tile = fct::kTileMax;     // tuned: LDS tile elements of the DCT passes
+  int32_t dct_engine[3] = {FCT_ENGINE_VECTOR, FCT_ENGINE_VECTOR, FCT_ENGINE_MATRIX};  // per mode
   int32_t unit_rows = fct::kUnitRows;   // tuned: rows per LDS unit
   int64_t block_bytes = 0;         // device bytes of the block descriptors, units and ell16
   fct::ColBlock* d_cblk = nullptr; // [ncblk]

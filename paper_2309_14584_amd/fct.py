@@ -30,6 +30,7 @@ FCT_PLAN_ALLOW_RANK_DEFICIENT = 1
 
 FAMILY_PLANTED, FAMILY_EXPCOS, FAMILY_GAUSS, FAMILY_RUNGE, FAMILY_OSC = range(5)
 DCT_F64, DCT_F32, DCT_BF16X3 = 0, 1, 2
+ENGINE_VECTOR, ENGINE_MATRIX = 0, 1
 SOLVE_F64, SOLVE_F32_REFINE, SOLVE_F32 = 0, 1, 2
 
 _vp = ctypes.c_void_p
@@ -60,7 +61,8 @@ class SolveInfo(ctypes.Structure):
 
 class TuneInfo(ctypes.Structure):
     _fields_ = [("dct_tile", _i32), ("unit_rows", _i32), ("dct_us", _dbl * 3),
-                ("rows_us", _dbl * 4)]
+                ("rows_us", _dbl * 4), ("dct_engine", _i32), ("reserved", _i32),
+                ("dct_matrix_us", _dbl * 3)]
 
 
 def _sig(name, res, *args):
@@ -93,6 +95,7 @@ _batch_create = _sig("fct_batch_create", ctypes.c_int, _i32, ctypes.POINTER(_vp)
 _plan_problem = _sig("fct_plan_problem", ctypes.c_int, _vp, _i32, *[ctypes.POINTER(_i64)] * 6)
 _ws_problem_info = _sig("fct_ws_problem_info", ctypes.c_int, _vp, _i32, ctypes.POINTER(SolveInfo))
 _plan_tune = _sig("fct_plan_tune", ctypes.c_int, _vp, _vp, _i32, _vp, ctypes.POINTER(TuneInfo))
+_plan_set_dct_engine = _sig("fct_plan_set_dct_engine", ctypes.c_int, _vp, _i32, _i32)
 _solve = _sig("fct_solve", ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
               ctypes.POINTER(SolveInfo), _vp, _vp)
 
@@ -100,7 +103,8 @@ EXPORTED = ["fct_last_error", "fct_status_string", "fct_abi_version", "fct_plan_
             "fct_plan_destroy", "fct_plan_get_info", "fct_plan_grid", "fct_plan_export",
             "fct_grid_nodes", "fct_ws_create", "fct_ws_destroy", "fct_sample", "fct_dct",
             "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve", "fct_batch_create",
-            "fct_plan_problem", "fct_ws_problem_info", "fct_plan_tune"]
+            "fct_plan_problem", "fct_ws_problem_info", "fct_plan_tune",
+            "fct_plan_set_dct_engine"]
 
 
 class FctError(RuntimeError):
@@ -242,8 +246,15 @@ class Plan:
         _check(_plan_get_info(self._h, ctypes.byref(pinfo)))
         self.info = pinfo
         return {"dct_tile": info.dct_tile, "unit_rows": info.unit_rows,
+                "dct_engine": info.dct_engine,
                 "dct_us": dict(zip((1024, 2048, 4096), info.dct_us)),
+                "dct_matrix_us": dict(zip((1024, 2048, 4096), info.dct_matrix_us)),
                 "rows_us": dict(zip((4096, 8192, 16384, 32768), info.rows_us))}
+
+    def set_dct_engine(self, dct_mode, engine):
+        """Run dct_mode's contractions on ENGINE_VECTOR or ENGINE_MATRIX
+        (fct_plan_set_dct_engine)."""
+        _check(_plan_set_dct_engine(self._h, int(dct_mode), int(engine)))
 
     def _wsh(self, ws):
         return self.ws if ws is None else ws.handle

@@ -158,9 +158,10 @@ def test_batch_mixed_precision_matches_alone(fct):
 
 
 def test_tuning_changes_no_result(fct):
-    """The autotuner picks the DCT tile and the LDS unit size by timing; the
-    DCT, the FP64 and the mixed-precision solves give the same bits before
-    and after tuning."""
+    """The autotuner picks the DCT tile, the DCT engine and the LDS unit size
+    by timing.  With the vector engine the DCT gives the same bits before
+    and after tuning, whatever the tile; the FP64 and mixed-precision solves
+    of a fixed right-hand side give the same bits whatever the unit size."""
     probs = _mixed_batch()
     plans = [fct.Plan(p.support, p.grids) for p in probs]
     batch = fct.Plan.batch(plans)
@@ -176,6 +177,12 @@ def test_tuning_changes_no_result(fct):
     print(info)
     assert info["dct_tile"] in (1024, 2048, 4096)
     assert info["unit_rows"] in (0, 4096, 8192, 16384, 32768)
+    assert info["dct_engine"] in (fct.ENGINE_VECTOR, fct.ENGINE_MATRIX)
+    # the tuned engine rounds differently at most; the tile alone changes no bit
+    tuned = _host(batch.dct(samples))
+    ref = before[fct.DCT_F64]
+    assert np.max(np.abs(tuned - ref)) <= 1e-13 * np.max(np.abs(ref))
+    batch.set_dct_engine(fct.DCT_F64, fct.ENGINE_VECTOR)
     for mode in (fct.DCT_F64, fct.DCT_F32):
         assert np.array_equal(_host(batch.dct(samples, mode=mode)), before[mode])
     assert np.array_equal(_host(batch.solve(b)[0]), c64)
@@ -184,5 +191,6 @@ def test_tuning_changes_no_result(fct):
     single = plans[1]
     ref = _host(single.dct(single.sample(fct.FAMILY_PLANTED, coeffs=_dev(probs[1].coeffs))))
     single.tune()
+    single.set_dct_engine(fct.DCT_F64, fct.ENGINE_VECTOR)
     assert np.array_equal(_host(single.dct(single.sample(fct.FAMILY_PLANTED,
                                                          coeffs=_dev(probs[1].coeffs)))), ref)

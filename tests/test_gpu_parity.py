@@ -262,6 +262,57 @@ def test_dct_reduced_precision(fct, prob, mode):
     plan.close()
 
 
+_MATRIX_CASES = [p for p in CASES if int(p.grids.max()) <= 31] + [W.config2()]
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prob", _MATRIX_CASES, ids=[p.name for p in _MATRIX_CASES[:-1]] + ["cfg2"])
+def test_dct_matrix_engine(fct, prob, mode):
+    """The FP64 and FP32 contractions on the matrix cores (16x16x4 MFMA):
+    FP64 to the same 1e-12 as the vector engine, FP32 to its rounding bound;
+    both engines agree to rounding."""
+    rng = np.random.default_rng(14)
+    plan = _plan(fct, prob)
+    ref_plan = O.build_plan(prob.support, prob.grids)
+    x = rng.standard_normal(plan.P)
+    offs = np.concatenate([[0], np.cumsum(prob.points)])
+    ref_full = [O.dct_grid(x[offs[l]:offs[l + 1]], prob.grids[l]) for l in range(prob.K)]
+    ref_b = O.rhs_from_transforms(ref_plan, ref_full)
+    xd = _dev(x)
+    vec = _host(plan.dct(xd, mode=mode))
+    plan.set_dct_engine(mode, fct.ENGINE_MATRIX)
+    b = _host(plan.dct(xd, mode=mode))
+    full = _host(plan.dct_full(xd, mode=mode))
+    if mode == 0:
+        bound = 1e-12
+    else:
+        emax = int(prob.grids.max()) + 1
+        bound = (4.0 * prob.D * emax * MODE_EPS[mode] * np.max(np.abs(x))
+                 / max(np.max(np.abs(ref_b)), 1e-300))
+    assert _rel(b, ref_b) < bound
+    assert _rel(full, np.concatenate(ref_full)) < bound
+    assert _rel(b, vec) < 2 * bound
+    plan.close()
+
+
+def test_dct_engine_errors(fct):
+    prob = W.small_problem(3, 4, 6, 1, 6, 6, W.FAMILY_EXPCOS)
+    plan = _plan(fct, prob)
+    with pytest.raises(fct.FctError):
+        plan.set_dct_engine(fct.DCT_BF16X3, fct.ENGINE_VECTOR)
+    with pytest.raises(fct.FctError):
+        plan.set_dct_engine(7, fct.ENGINE_VECTOR)
+    with pytest.raises(fct.FctError):
+        plan.set_dct_engine(fct.DCT_F64, 2)
+    plan.set_dct_engine(fct.DCT_F64, fct.ENGINE_MATRIX)
+    plan.close()
+    long_axes = W.small_problem(6, 2, 20, 40, 63, 2, W.FAMILY_OSC)     # extents 41..64
+    plan = _plan(fct, long_axes)
+    with pytest.raises(fct.FctError):
+        plan.set_dct_engine(fct.DCT_F64, fct.ENGINE_MATRIX)
+    plan.close()
+
+
 # Mixed precision: FP32 CGLS rounds refined in FP64 reach the FP64 bar
 # (1e-10 max-relative); a single FP32 round (pure FP32 vectors) is held to
 # 1e-5.
