@@ -44,7 +44,7 @@ __all__ = [
     "sample_function", "sample_problem", "rhs_from_transforms",
     "dense_A", "sparse_A", "lstsq_qr", "lstsq_normal", "rank_check",
     "gram_matrix", "normal_residual", "fct_solve", "max_rel_err", "lstsq_lsqr",
-    "mean_l2_err", "fold_injective",
+    "mean_l2_err", "fold_injective", "evaluate_expansion", "linf_error",
 ]
 
 
@@ -510,3 +510,39 @@ def mean_l2_err(c, c_ref) -> float:
     """||c - c_ref||_2 / N, the paper's mean l2 coefficient error (Sec. 4.5.1)."""
     c = np.asarray(c, dtype=np.float64)
     return float(np.linalg.norm(c - np.asarray(c_ref)) / c.size)
+
+
+# ---------------------------------------------------------------------------
+# Evaluation of a recovered expansion (Sec. 2, definition of the Chebyshev
+# expansion on the support; Sec. 4 measures accuracy at random points)
+# ---------------------------------------------------------------------------
+
+def evaluate_expansion(support, coeffs, X, chunk: int = 256) -> np.ndarray:
+    """p(x) = sum_j c_j prod_i T_{n_ji}(x_i) at every row x of X ([m][D]).
+
+    Per point and dimension the values T_0..T_nmax come from the three-term
+    recurrence; each term is the product over the dimensions, and the terms
+    are summed in support order.  Points are taken `chunk` at a time.
+    """
+    S = np.asarray(support, dtype=np.int64)
+    c = np.asarray(coeffs, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    m, D = X.shape
+    if S.shape[1] != D:
+        raise ValueError("support and points differ in dimension")
+    nmax = int(S.max()) if S.size else 0
+    out = np.empty(m)
+    for a in range(0, m, chunk):
+        xb = X[a:a + chunk]
+        # T[i][k][point]
+        T = [cheb_T_recurrence(nmax, xb[:, i]) for i in range(D)]
+        terms = np.ones((S.shape[0], xb.shape[0]))
+        for i in range(D):
+            terms *= T[i][S[:, i]]
+        out[a:a + chunk] = c @ terms
+    return out
+
+
+def linf_error(values, reference) -> float:
+    """max |values - reference| (the sup-norm error at sample points)."""
+    return float(np.max(np.abs(np.asarray(values) - np.asarray(reference))))

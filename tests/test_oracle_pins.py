@@ -475,3 +475,68 @@ def test_serving_pool_small_jobs_recover():
     for a in range(20):
         for b in range(a + 1, 20):
             assert any(a in r and b in r for r in res)
+
+
+# --------------------------------------------------------------------------
+# Evaluation of an expansion at arbitrary points (Sec. 2 definition)
+# --------------------------------------------------------------------------
+
+def _dense_tensor(support, coeffs, D):
+    S = np.asarray(support)
+    shape = tuple(int(S[:, i].max()) + 1 for i in range(D))
+    t = np.zeros(shape)
+    for row, c in zip(S, coeffs):
+        t[tuple(row)] += c
+    return t
+
+
+@pytest.mark.parametrize("D,d", [(1, 9), (2, 7), (3, 5)])
+def test_evaluate_expansion_against_numpy_chebval(D, d):
+    """numpy's Chebyshev module (Clenshaw recurrences) on the dense tensor."""
+    rng = np.random.default_rng(41 + D)
+    S = W.total_degree_support(D, d)
+    c = rng.standard_normal(S.shape[0])
+    X = rng.uniform(-1, 1, size=(37, D))
+    t = _dense_tensor(S, c, D)
+    ref = {1: lambda: npc.chebval(X[:, 0], t),
+           2: lambda: npc.chebval2d(X[:, 0], X[:, 1], t),
+           3: lambda: npc.chebval3d(X[:, 0], X[:, 1], X[:, 2], t)}[D]()
+    got = O.evaluate_expansion(S, c, X, chunk=8)
+    assert O.linf_error(got, ref) < 1e-13 * np.sum(np.abs(c))
+
+
+def test_evaluate_expansion_cosine_closed_form():
+    """T_n(cos theta) = cos(n theta): one term per coefficient, D = 6."""
+    rng = np.random.default_rng(47)
+    S = W.euclidean_degree_support(6, 4.5)
+    theta = rng.uniform(0, np.pi, size=(11, 6))
+    X = np.cos(theta)
+    for j in rng.choice(S.shape[0], size=12, replace=False):
+        c = np.zeros(S.shape[0])
+        c[j] = 1.0
+        ref = np.prod(np.cos(S[j][None, :] * theta), axis=1)
+        assert O.linf_error(O.evaluate_expansion(S, c, X), ref) < 1e-13
+
+
+def test_evaluate_expansion_at_nodes_obeys_aliasing():
+    """Values at the nodes of a grid, transformed by the DCT-I, are A c at
+    the grid's bins (the aliasing identity, eq. aliasing_matrix_nd_diff)."""
+    prob = W.small_problem(49, 3, 6, 2, 5, 3)
+    plan = O.build_plan(prob.support, prob.grids)
+    A = O.dense_A(plan)
+    transforms = []
+    for g in prob.grids:
+        X = np.stack(np.meshgrid(*[O.lobatto_nodes(int(N)) for N in g], indexing="ij"),
+                     axis=-1).reshape(-1, 3)
+        transforms.append(O.dct_grid(O.evaluate_expansion(prob.support, prob.coeffs, X), g))
+    b = O.rhs_from_transforms(plan, transforms)
+    assert np.max(np.abs(b - A @ prob.coeffs)) < 1e-13 * np.sum(np.abs(prob.coeffs))
+
+
+def test_euclidean_support_is_the_ball():
+    """S^2_{d,D} by brute force over the cube (Sec. 2)."""
+    for D, d in [(2, 5.0), (3, 4.2), (5, 3.0)]:
+        S = W.euclidean_degree_support(D, d)
+        cube = np.array(list(itertools.product(range(int(d) + 1), repeat=D)))
+        ref = cube[np.sum(cube ** 2, axis=1) <= d * d + 1e-9]
+        assert np.array_equal(S, ref)       # both lexicographic
