@@ -279,6 +279,19 @@ fct_status fct_dct(const fct_plan* plan, const double* d_samples, double* d_b,
 fct_status fct_dct_full(const fct_plan* plan, const double* d_samples, double* d_out,
                         int32_t mode, fct_ws* ws, hipStream_t stream);
 
+/* ---- evaluation (Sec. 2: p(x) = sum over the support of c_n T_n(x)) ------
+ * d_f[q] = sum_j d_c[j] prod_i T_{S[j][i]}(d_x[q * D + i]) for 0 <= q < m:
+ * the expansion with coefficients d_c (double [n], the plan's support
+ * order) at m arbitrary points d_x (double, row-major [m][D]; any real
+ * coordinates, T_k from T_{k+1} = 2 x T_k - T_{k-1}).  d_f double [m].
+ * Each point's terms are summed in a fixed order (reproducible).  Single-
+ * problem plans only; FCT_EINVAL for a batch plan, m < 0, NULL pointers, or
+ * a per-point table D * (max support entry + 1) above the LDS capacity
+ * (about 240 values).  m = 0 does nothing.  Asynchronous on `stream`.
+ */
+fct_status fct_eval(const fct_plan* plan, const double* d_c, int64_t m, const double* d_x,
+                    double* d_f, hipStream_t stream);
+
 /* ---- operator (eq. main_linear_system) ----------------------------------
  * fct_apply_A:  d_q[r] = sum over support rows j aliased to row r of d_c[j]
  *               (double [n] -> double [M]); summed in perm order.

@@ -473,6 +473,7 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   p->nprob = 1;
   p->D = D; p->K = K; p->n = n;
   p->grids.assign(grids, grids + (size_t)K * D);
+  for (int64_t t = 0; t < n * D; ++t) p->smax = std::max(p->smax, support[t]);
   p->grid_D.assign((size_t)K, D);
   p->grid_goff.resize((size_t)K + 1);
   for (int l = 0; l <= K; ++l) p->grid_goff[(size_t)l] = (int64_t)l * D;
@@ -876,6 +877,27 @@ fct_status fct_dct_full(const fct_plan* p, const double* d_samples, double* d_ou
   for (const auto& lv : p->fwd_full)
     FCT_HIP(launch_dct_level(lv, mode, p->dct_engine[mode], d_samples, nullptr, d_out,
                                      p->d_cmat, p->d_cmat32, p->d_bin_id, s));
+  return FCT_OK;
+}
+
+fct_status fct_eval(const fct_plan* p, const double* d_c, int64_t m, const double* d_x,
+                    double* d_f, hipStream_t s) {
+  if (!p) { set_error("NULL plan"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  if (p->nprob != 1 || !p->d_support) {
+    set_error("evaluation needs a single-problem plan (use each problem's own plan)");
+    return FCT_EINVAL;
+  }
+  if (m < 0) { set_error("m = %lld < 0", (long long)m); return FCT_EINVAL; }
+  if (m == 0) return FCT_OK;
+  if (!d_c || !d_x || !d_f) { set_error("NULL argument"); return FCT_EINVAL; }
+  const int nk = p->smax + 1;
+  if (eval_lds_bytes(p->D, nk) > (size_t)160 * 1024 || p->D * nk > 65535) {
+    set_error("evaluation table of D * (max degree + 1) = %d values per point exceeds the LDS",
+              p->D * nk);
+    return FCT_EINVAL;
+  }
+  FCT_HIP(launch_eval(p->d_support, d_c, p->n, p->D, nk, m, d_x, d_f, s));
   return FCT_OK;
 }
 

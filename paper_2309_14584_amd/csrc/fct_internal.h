@@ -128,6 +128,11 @@ hipError_t launch_sample(int family, const SampleParams& prm, int D, const Sampl
                          int ndesc, int64_t tiles, const int32_t* grids, const double* nodes,
                          double* out, hipStream_t s);
 
+// evaluation of the expansion at arbitrary points (nk = max support entry + 1)
+size_t eval_lds_bytes(int D, int nk);
+hipError_t launch_eval(const int32_t* support, const double* c, int64_t n, int D, int nk,
+                       int64_t m, const double* X, double* f, hipStream_t s);
+
 // Work decomposition of the CGLS kernels.  A plan holds one or more
 // independent problems (a batch); every workgroup of the row (column)
 // kernel covers up to kBlock rows (columns) of a single problem.
@@ -266,6 +271,7 @@ struct fct_plan {
   int64_t total_points = 0;
   int64_t max_points = 0;
   int32_t maxdeg = 0;
+  int32_t smax = 0;                // largest support entry (single problem)
   std::vector<int32_t> grid_D;     // [K] dimension of each grid's problem
   std::vector<int64_t> grid_goff;  // [K+1] offsets of each grid's degrees in `grids`
   std::vector<int32_t> grids;      // degrees, grid after grid

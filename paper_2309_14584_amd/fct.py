@@ -31,6 +31,7 @@ FCT_PLAN_ALLOW_RANK_DEFICIENT = 1
 FAMILY_PLANTED, FAMILY_EXPCOS, FAMILY_GAUSS, FAMILY_RUNGE, FAMILY_OSC = range(5)
 DCT_F64, DCT_F32, DCT_BF16X3 = 0, 1, 2
 ENGINE_VECTOR, ENGINE_MATRIX = 0, 1
+ABI_VERSION = 2          # FCT_ABI_VERSION of the header this binding follows
 SOLVE_F64, SOLVE_F32_REFINE, SOLVE_F32 = 0, 1, 2
 
 _vp = ctypes.c_void_p
@@ -96,6 +97,7 @@ _plan_problem = _sig("fct_plan_problem", ctypes.c_int, _vp, _i32, *[ctypes.POINT
 _ws_problem_info = _sig("fct_ws_problem_info", ctypes.c_int, _vp, _i32, ctypes.POINTER(SolveInfo))
 _plan_tune = _sig("fct_plan_tune", ctypes.c_int, _vp, _vp, _i32, _vp, ctypes.POINTER(TuneInfo))
 _plan_set_dct_engine = _sig("fct_plan_set_dct_engine", ctypes.c_int, _vp, _i32, _i32)
+_eval = _sig("fct_eval", ctypes.c_int, _vp, _vp, _i64, _vp, _vp, _vp)
 _solve = _sig("fct_solve", ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
               ctypes.POINTER(SolveInfo), _vp, _vp)
 
@@ -104,7 +106,7 @@ EXPORTED = ["fct_last_error", "fct_status_string", "fct_abi_version", "fct_plan_
             "fct_grid_nodes", "fct_ws_create", "fct_ws_destroy", "fct_sample", "fct_dct",
             "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve", "fct_batch_create",
             "fct_plan_problem", "fct_ws_problem_info", "fct_plan_tune",
-            "fct_plan_set_dct_engine"]
+            "fct_plan_set_dct_engine", "fct_eval"]
 
 
 class FctError(RuntimeError):
@@ -343,6 +345,21 @@ class Plan:
         _check(_dct_full(self._h, _ptr(samples, torch.float64, self.P, "samples"),
                          _ptr(out, torch.float64, self.P, "out"), mode, self._wsh(ws),
                          _stream(stream)))
+        return out
+
+    def eval(self, c, x, out=None, stream=None):
+        """The expansion with coefficients c (device double [n]) at the
+        points x (device double [m, D]) -> device double [m] (fct_eval)."""
+        torch = _torch()
+        m = int(x.shape[0]) if x.dim() == 2 else 0
+        if x.dim() != 2 or (m and int(x.shape[1]) != self.D):
+            raise ValueError(f"x must have shape [m, {self.D}]")
+        out = self._empty(m) if out is None else out
+        if m == 0:
+            return out
+        _check(_eval(self._h, _ptr(c, torch.float64, self.n, "c"), m,
+                     _ptr(x, torch.float64, m * self.D, "x"),
+                     _ptr(out, torch.float64, m, "out"), _stream(stream)))
         return out
 
     def apply_A(self, c, out=None, stream=None):

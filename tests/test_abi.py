@@ -33,7 +33,7 @@ def test_header_symbols_exported(fct):
 
 
 def test_abi_version_and_strings(fct):
-    assert fct.abi_version() == 2
+    assert fct.abi_version() == fct.ABI_VERSION == 2
     assert fct._status_string(fct.FCT_ERANK) == b"FCT_ERANK"
     assert fct._status_string(99) == b"FCT_UNKNOWN"
 
