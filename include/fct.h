@@ -287,7 +287,7 @@ fct_status fct_dct_full(const fct_plan* plan, const double* d_samples, double* d
  * Each point's terms are summed in a fixed order (reproducible).  Single-
  * problem plans only; FCT_EINVAL for a batch plan, m < 0, NULL pointers, or
  * a per-point table D * (max support entry + 1) above the LDS capacity
- * (about 240 values).  m = 0 does nothing.  Asynchronous on `stream`.
+ * (about 290 values).  m = 0 does nothing.  Asynchronous on `stream`.
  */
 fct_status fct_eval(const fct_plan* plan, const double* d_c, int64_t m, const double* d_x,
                     double* d_f, hipStream_t stream);

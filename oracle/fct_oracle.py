@@ -45,6 +45,7 @@ __all__ = [
     "dense_A", "sparse_A", "lstsq_qr", "lstsq_normal", "rank_check",
     "gram_matrix", "normal_residual", "fct_solve", "max_rel_err", "lstsq_lsqr",
     "mean_l2_err", "fold_injective", "evaluate_expansion", "linf_error",
+    "function_values",
 ]
 
 
@@ -541,6 +542,11 @@ def evaluate_expansion(support, coeffs, X, chunk: int = 256) -> np.ndarray:
             terms *= T[i][S[:, i]]
         out[a:a + chunk] = c @ terms
     return out
+
+
+def function_values(family: int, params, X) -> np.ndarray:
+    """The test function of `family` at the rows of X ([m][D])."""
+    return _function_at(family, params, np.asarray(X, dtype=np.float64))
 
 
 def linf_error(values, reference) -> float:

@@ -20,17 +20,16 @@ namespace {
 constexpr int kEvalPoints = 64;            // points per workgroup (lanes)
 constexpr int kEvalWaves = 16;             // waves per workgroup
 constexpr int kEvalThreads = kEvalPoints * kEvalWaves;
-constexpr int kEvalChunk = 1024;           // support rows staged at a time
 constexpr int kEvalIlp = 4;                // terms a wave interleaves
 
 __global__ __launch_bounds__(kEvalThreads) void eval_kernel(
     const int32_t* __restrict__ support, const double* __restrict__ c, int64_t n, int D, int nk,
-    int64_t m, const double* __restrict__ X, double* __restrict__ f) {
+    int chunk, int64_t m, const double* __restrict__ X, double* __restrict__ f) {
   extern __shared__ __align__(16) unsigned char eval_smem[];
   double* T = reinterpret_cast<double*>(eval_smem);                 // [D * nk][64]
-  double* coef = T + (size_t)D * nk * kEvalPoints;                  // [kEvalChunk]
-  double* part = coef + kEvalChunk;                                 // [kEvalWaves][64]
-  uint16_t* off = reinterpret_cast<uint16_t*>(part + kEvalThreads); // [kEvalChunk][D]
+  double* part = T + (size_t)D * nk * kEvalPoints;                  // [kEvalWaves][64]
+  double* coef = part + kEvalThreads;                               // [chunk]
+  uint16_t* off = reinterpret_cast<uint16_t*>(coef + chunk);        // [chunk][D]
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t pt = (int64_t)blockIdx.x * kEvalPoints + lane;
@@ -52,8 +51,8 @@ __global__ __launch_bounds__(kEvalThreads) void eval_kernel(
   }
 
   double acc = 0.0;
-  for (int64_t j0 = 0; j0 < n; j0 += kEvalChunk) {
-    const int cnt = (int)min((int64_t)kEvalChunk, n - j0);
+  for (int64_t j0 = 0; j0 < n; j0 += chunk) {
+    const int cnt = (int)min((int64_t)chunk, n - j0);
     __syncthreads();                       // table written / previous chunk consumed
     for (int e = threadIdx.x; e < cnt * D; e += kEvalThreads) {
       const int jj = e / D, i = e - jj * D;
@@ -91,22 +90,34 @@ __global__ __launch_bounds__(kEvalThreads) void eval_kernel(
 
 }  // namespace
 
-size_t eval_lds_bytes(int D, int nk) {
-  return sizeof(double) * ((size_t)D * nk * kEvalPoints + kEvalChunk + kEvalThreads) +
-         sizeof(uint16_t) * (size_t)kEvalChunk * D;
+// Support rows staged per chunk: as many as fit next to the table (at most
+// 1024, a multiple of 16); 0 if the table leaves no room for 16.
+int eval_chunk(int D, int nk) {
+  const int64_t fixed = (int64_t)sizeof(double) * ((int64_t)D * nk * kEvalPoints + kEvalThreads);
+  const int64_t room = (int64_t)kEvalLdsMax - fixed;
+  if (room <= 0) return 0;
+  int64_t chunk = room / (int64_t)(sizeof(double) + sizeof(uint16_t) * D);
+  chunk = std::min<int64_t>(chunk, 1024) & ~int64_t(15);
+  return chunk >= 16 ? (int)chunk : 0;
+}
+
+size_t eval_lds_bytes(int D, int nk, int chunk) {
+  return sizeof(double) * ((size_t)D * nk * kEvalPoints + kEvalThreads + chunk) +
+         sizeof(uint16_t) * (size_t)chunk * D;
 }
 
 hipError_t launch_eval(const int32_t* support, const double* c, int64_t n, int D, int nk,
                        int64_t m, const double* X, double* f, hipStream_t s) {
   if (m == 0) return hipSuccess;
   const int64_t blocks = ceil_div(m, kEvalPoints);
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t lds = eval_lds_bytes(D, nk);
+  const int chunk = eval_chunk(D, nk);
+  if (blocks > 0x7fffffffLL || chunk == 0 || D * nk > 65535) return hipErrorInvalidValue;
+  const size_t lds = eval_lds_bytes(D, nk, chunk);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&eval_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(eval_kernel, dim3((unsigned)blocks), dim3(kEvalThreads), lds, s, support, c,
-                     n, D, nk, m, X, f);
+                     n, D, nk, chunk, m, X, f);
   return hipGetLastError();
 }
 

@@ -892,7 +892,7 @@ fct_status fct_eval(const fct_plan* p, const double* d_c, int64_t m, const doubl
   if (m == 0) return FCT_OK;
   if (!d_c || !d_x || !d_f) { set_error("NULL argument"); return FCT_EINVAL; }
   const int nk = p->smax + 1;
-  if (eval_lds_bytes(p->D, nk) > (size_t)160 * 1024 || p->D * nk > 65535) {
+  if (eval_chunk(p->D, nk) == 0 || p->D * nk > 65535) {
     set_error("evaluation table of D * (max degree + 1) = %d values per point exceeds the LDS",
               p->D * nk);
     return FCT_EINVAL;

@@ -129,7 +129,9 @@ hipError_t launch_sample(int family, const SampleParams& prm, int D, const Sampl
                          double* out, hipStream_t s);
 
 // evaluation of the expansion at arbitrary points (nk = max support entry + 1)
-size_t eval_lds_bytes(int D, int nk);
+constexpr int kEvalLdsMax = 160 * 1024;   // LDS of one workgroup
+int eval_chunk(int D, int nk);            // 0: the per-point table does not fit
+size_t eval_lds_bytes(int D, int nk, int chunk);
 hipError_t launch_eval(const int32_t* support, const double* c, int64_t n, int D, int nk,
                        int64_t m, const double* X, double* f, hipStream_t s);
 
