@@ -239,6 +239,19 @@ def bench_precision(fct, torch, steps):
         res[dname] = ent
     plan.dct(samples, out=b)
     tinfo = plan.solve(b, out=c, timing=True)[1]
+    # the recovered 646,646-term expansion at 1000 random points (fct_eval)
+    X = np.random.default_rng(6).uniform(-1, 1, size=(1000, prob.D))
+    xd = torch.tensor(X, dtype=torch.float64, device=dev)
+    fv = plan.eval(c, xd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.eval(c, xd, out=fv)
+    torch.cuda.synchronize()
+    t_eval = time.perf_counter() - t0
+    fx = W.family_values(prob.family, prob.params, X)
+    res["accuracy"] = {"points": 1000, "eval_ms": 1e3 * t_eval,
+                       "eval_terms_per_s": 1000 * plan.n / t_eval,
+                       "sup_norm_error": float(np.max(np.abs(fv.cpu().numpy() - fx)))}
     algo = rows_kernel_bytes(plan)
     ach = algo / (tinfo.rows_kernel_us * 1e-6) / 1e9
     res["roofline"] = {"bound": "hbm", "kernel": "cgls_rows_kernel", "achieved": ach,
@@ -422,6 +435,21 @@ def main():
     torch.cuda.synchronize()
     out["roofline"] = roofline_rows(plan, tinfo.rows_kernel_us)
     out["roofline"]["cols_kernel_us"] = tinfo.cols_kernel_us
+    # accuracy of the recovered expansion (the paper's sup-norm error at
+    # random points), evaluated on the GPU (fct_eval); f itself on the host
+    X = np.random.default_rng(5).uniform(-1, 1, size=(5000, prob.D))
+    xd = torch.tensor(X, dtype=torch.float64, device=dev)
+    fv = plan.eval(c, xd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        plan.eval(c, xd, out=fv)
+    torch.cuda.synchronize()
+    t_eval = (time.perf_counter() - t0) / 10
+    fx = W.family_values(prob.family, prob.params, X)
+    out["accuracy"] = {"points": 5000, "sup_norm_error": float(np.max(np.abs(fv.cpu().numpy() - fx))),
+                       "max_abs_f": float(np.max(np.abs(fx))), "eval_ms": 1e3 * t_eval,
+                       "eval_terms_per_s": 5000 * prob.n / t_eval}
     plan.close()
     if not args.skip_batched:
         out["batched"] = bench_batched(fct, torch, args.batched_steps,

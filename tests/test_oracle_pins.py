@@ -540,3 +540,15 @@ def test_euclidean_support_is_the_ball():
         cube = np.array(list(itertools.product(range(int(d) + 1), repeat=D)))
         ref = cube[np.sum(cube ** 2, axis=1) <= d * d + 1e-9]
         assert np.array_equal(S, ref)       # both lexicographic
+
+
+def test_workload_family_values_match_the_oracle():
+    """The workloads' analytic test functions equal the oracle's (two
+    independent codings of the same definitions)."""
+    rng = np.random.default_rng(53)
+    X = rng.uniform(-1, 1, size=(50, 4))
+    for fam, prm in [(W.FAMILY_EXPCOS, rng.uniform(0.2, 2, 8)),
+                     (W.FAMILY_GAUSS, np.concatenate([[0.8], rng.uniform(-.5, .5, 4)])),
+                     (W.FAMILY_RUNGE, [10.0]), (W.FAMILY_OSC, [])]:
+        assert np.allclose(W.family_values(fam, prm, X), O.function_values(fam, prm, X),
+                           rtol=1e-14, atol=1e-15)

@@ -421,6 +421,24 @@ def serving_pool(seed: int = 4, per_type: int = 16, extra_grids=None):
     return jobs
 
 
+def family_values(family: int, params, X) -> np.ndarray:
+    """The analytic test functions (the inputs the workloads sample) at the
+    rows of X ([m][D]), for measuring the accuracy of a recovered expansion."""
+    X = np.asarray(X, dtype=np.float64)
+    D = X.shape[1]
+    p = np.asarray(params, dtype=np.float64)
+    if family == FAMILY_EXPCOS:
+        return np.exp(-(X * X) @ p[:D]) * np.cos(X @ p[D:2 * D])
+    if family == FAMILY_GAUSS:
+        return np.exp(-((X - p[1:1 + D]) ** 2).sum(axis=1) / (2.0 * p[0] * p[0]))
+    if family == FAMILY_RUNGE:
+        return 1.0 / (1.0 + p[0] * (X * X).sum(axis=1))
+    if family == FAMILY_OSC:
+        r2 = (X * X).sum(axis=1)
+        return np.sin(3.0 * np.cos(3.0 * np.exp(r2))) + np.exp(np.sin(3.0 * X.sum(axis=1)))
+    raise ValueError(f"no analytic values for family {family}")
+
+
 def poisson_arrivals(seed: int, rate: float, duration: float):
     """Arrival times (seconds) of a Poisson stream with the given rate."""
     _, _, g_arr = streams(seed)
