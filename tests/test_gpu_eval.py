@@ -132,3 +132,24 @@ def test_recovered_expansion_accuracy(fct):
     # the least-squares minimiser's own error (QR minimiser: 1.71e-2)
     assert abs(linf - 1.7071e-2) < 1e-4
     plan.close()
+
+
+@pytest.mark.parametrize("family", [W.FAMILY_PLANTED, W.FAMILY_EXPCOS], ids=["planted", "expcos"])
+def test_euclidean_support_full_path(fct, family):
+    """A Euclidean-degree support S^2 (D=5, |n|_2 <= 6) through the whole
+    path: plan, sampling, DCT, CGLS, evaluation -- against the oracle."""
+    prob = W.euclidean_problem(family=family)
+    plan = fct.Plan(prob.support, prob.grids)
+    oplan = O.build_plan(prob.support, prob.grids)
+    assert plan.M == oplan.M
+    coeffs = _dev(prob.coeffs) if prob.coeffs is not None else None
+    c, info = plan.solve(plan.dct(plan.sample(prob.family, prob.params, coeffs=coeffs)))
+    ch = c.cpu().numpy()
+    c_ref, _, _ = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "qr")
+    assert info.converged and O.max_rel_err(ch, c_ref) < 1e-10
+    if prob.coeffs is not None:
+        assert O.max_rel_err(ch, prob.coeffs) < 1e-10
+    X = np.random.default_rng(8).uniform(-1, 1, size=(777, 5))
+    got = plan.eval(c, _dev(X)).cpu().numpy()
+    assert O.linf_error(got, O.evaluate_expansion(prob.support, ch, X)) <= 1e-12 * np.abs(ch).sum()
+    plan.close()

@@ -552,3 +552,14 @@ def test_workload_family_values_match_the_oracle():
                      (W.FAMILY_RUNGE, [10.0]), (W.FAMILY_OSC, [])]:
         assert np.allclose(W.family_values(fam, prm, X), O.function_values(fam, prm, X),
                            rtol=1e-14, atol=1e-15)
+
+
+def test_euclidean_workload_recovers_planted():
+    """The Euclidean-degree workload's grid count makes A full rank (Alg. 2's
+    stopping rule) and the oracle recovers a planted expansion exactly."""
+    prob = W.euclidean_problem()
+    plan = O.build_plan(prob.support, prob.grids)
+    full, kappa = O.rank_check(plan)
+    assert full and kappa < 1e2
+    c, _, _ = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "qr")
+    assert O.max_rel_err(c, prob.coeffs) < 1e-12

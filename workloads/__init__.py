@@ -254,6 +254,29 @@ def small_problem(seed: int, D: int, d: int, lo: int, hi: int, K: int,
     return Problem(f"small_D{D}_d{d}_K{K}_s{seed}", S, grids, family, params, c, seed)
 
 
+# Euclidean-degree workload: S^2 of radius 6 in D = 5 (2,673 coefficients),
+# i.i.d. U{2..6} grids; 9 grids is where the oracle's rank test (the stopping
+# rule of Alg. 2) first finds A full rank for seed 11 (kappa ~ 9).
+EUCLID_GRIDS = 9
+
+
+def euclidean_problem(seed: int = 11, family: int = FAMILY_PLANTED) -> Problem:
+    """D = 5, |n|_2 <= 6 (Sec. 2, S^2_{d,D}) on EUCLID_GRIDS grids."""
+    g_grid = np.random.default_rng(seed)
+    S = euclidean_degree_support(5, 6.0)
+    grids = np.ascontiguousarray(g_grid.integers(2, 7, size=(EUCLID_GRIDS, 5)).astype(np.int32))
+    _, g_coef, _ = streams(seed)
+    c = None
+    params = np.zeros(0)
+    if family == FAMILY_PLANTED:
+        c = planted_coefficients(g_coef, S)
+    elif family == FAMILY_EXPCOS:
+        params = np.concatenate([g_coef.uniform(0.2, 1.0, size=5), g_coef.uniform(0.5, 2.0, size=5)])
+    else:
+        raise ValueError("euclidean_problem: planted or exp-cos")
+    return Problem(f"euclid_D5_r6_s{seed}_f{family}", S, grids, family, params, c, seed)
+
+
 def config3_problem(rng_grid, rng_coef, cap=50_000):
     """One problem of the batched workload: D ~ U{3..8}, d ~ U{6..16}, d
     lowered until C(D+d, d) <= cap; grids drawn as in Alg. 1 (dimensions in
