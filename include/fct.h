@@ -284,13 +284,17 @@ fct_status fct_dct_full(const fct_plan* plan, const double* d_samples, double* d
  * the expansion with coefficients d_c (double [n], the plan's support
  * order) at m arbitrary points d_x (double, row-major [m][D]; any real
  * coordinates, T_k from T_{k+1} = 2 x T_k - T_{k-1}).  d_f double [m].
- * Each point's terms are summed in a fixed order (reproducible).  Single-
- * problem plans only; FCT_EINVAL for a batch plan, m < 0, NULL pointers, or
- * a per-point table D * (max support entry + 1) above the LDS capacity
- * (about 290 values).  m = 0 does nothing.  Asynchronous on `stream`.
+ * ws (optional, the plan's workspace) lets few points with a long support
+ * run on the whole device: the support is cut into slices whose partial sums
+ * go to the workspace's scratch tensor and are added in slice order.  Each
+ * point's terms are summed in a fixed order for given (m, ws present), so
+ * results are reproducible.  Single-problem plans only; FCT_EINVAL for a
+ * batch plan, m < 0, NULL pointers, a workspace of another plan, or a
+ * per-point table D * (max support entry + 1) above the LDS capacity (about
+ * 290 values).  m = 0 does nothing.  Asynchronous on `stream`.
  */
 fct_status fct_eval(const fct_plan* plan, const double* d_c, int64_t m, const double* d_x,
-                    double* d_f, hipStream_t stream);
+                    double* d_f, fct_ws* ws, hipStream_t stream);
 
 /* ---- operator (eq. main_linear_system) ----------------------------------
  * fct_apply_A:  d_q[r] = sum over support rows j aliased to row r of d_c[j]

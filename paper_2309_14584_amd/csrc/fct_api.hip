@@ -881,7 +881,7 @@ fct_status fct_dct_full(const fct_plan* p, const double* d_samples, double* d_ou
 }
 
 fct_status fct_eval(const fct_plan* p, const double* d_c, int64_t m, const double* d_x,
-                    double* d_f, hipStream_t s) {
+                    double* d_f, fct_ws* ws, hipStream_t s) {
   if (!p) { set_error("NULL plan"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
   if (p->nprob != 1 || !p->d_support) {
@@ -897,7 +897,13 @@ fct_status fct_eval(const fct_plan* p, const double* d_c, int64_t m, const doubl
               p->D * nk);
     return FCT_EINVAL;
   }
-  FCT_HIP(launch_eval(p->d_support, d_c, p->n, p->D, nk, m, d_x, d_f, s));
+  if (ws) {
+    fct_status st = check_ws(p, ws);
+    if (st != FCT_OK) return st;
+  }
+  const int slices = eval_slices(p->n, p->D, nk, m, ws ? p->total_points : 0);
+  FCT_HIP(launch_eval(p->d_support, d_c, p->n, p->D, nk, m, d_x, d_f, slices,
+                      ws ? ws->d_scratch : nullptr, s));
   return FCT_OK;
 }
 

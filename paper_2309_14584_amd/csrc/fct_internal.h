@@ -132,8 +132,11 @@ hipError_t launch_sample(int family, const SampleParams& prm, int D, const Sampl
 constexpr int kEvalLdsMax = 160 * 1024;   // LDS of one workgroup
 int eval_chunk(int D, int nk);            // 0: the per-point table does not fit
 size_t eval_lds_bytes(int D, int nk, int chunk);
+// support slices for m points given scratch_elems doubles of scratch (>= 1)
+int eval_slices(int64_t n, int D, int nk, int64_t m, int64_t scratch_elems);
 hipError_t launch_eval(const int32_t* support, const double* c, int64_t n, int D, int nk,
-                       int64_t m, const double* X, double* f, hipStream_t s);
+                       int64_t m, const double* X, double* f, int slices, double* scratch,
+                       hipStream_t s);
 
 // Work decomposition of the CGLS kernels.  A plan holds one or more
 // independent problems (a batch); every workgroup of the row (column)

@@ -97,7 +97,7 @@ _plan_problem = _sig("fct_plan_problem", ctypes.c_int, _vp, _i32, *[ctypes.POINT
 _ws_problem_info = _sig("fct_ws_problem_info", ctypes.c_int, _vp, _i32, ctypes.POINTER(SolveInfo))
 _plan_tune = _sig("fct_plan_tune", ctypes.c_int, _vp, _vp, _i32, _vp, ctypes.POINTER(TuneInfo))
 _plan_set_dct_engine = _sig("fct_plan_set_dct_engine", ctypes.c_int, _vp, _i32, _i32)
-_eval = _sig("fct_eval", ctypes.c_int, _vp, _vp, _i64, _vp, _vp, _vp)
+_eval = _sig("fct_eval", ctypes.c_int, _vp, _vp, _i64, _vp, _vp, _vp, _vp)
 _solve = _sig("fct_solve", ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
               ctypes.POINTER(SolveInfo), _vp, _vp)
 
@@ -347,9 +347,11 @@ class Plan:
                          _stream(stream)))
         return out
 
-    def eval(self, c, x, out=None, stream=None):
+    def eval(self, c, x, out=None, stream=None, ws=None):
         """The expansion with coefficients c (device double [n]) at the
-        points x (device double [m, D]) -> device double [m] (fct_eval)."""
+        points x (device double [m, D]) -> device double [m] (fct_eval; the
+        plan's workspace lets the support be sliced across the device,
+        ws=False evaluates without one)."""
         torch = _torch()
         m = int(x.shape[0]) if x.dim() == 2 else 0
         if x.dim() != 2 or (m and int(x.shape[1]) != self.D):
@@ -359,7 +361,8 @@ class Plan:
             return out
         _check(_eval(self._h, _ptr(c, torch.float64, self.n, "c"), m,
                      _ptr(x, torch.float64, m * self.D, "x"),
-                     _ptr(out, torch.float64, m, "out"), _stream(stream)))
+                     _ptr(out, torch.float64, m, "out"),
+                     None if ws is False else self._wsh(ws), _stream(stream)))
         return out
 
     def apply_A(self, c, out=None, stream=None):

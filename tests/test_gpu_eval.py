@@ -153,3 +153,25 @@ def test_euclidean_support_full_path(fct, family):
     got = plan.eval(c, _dev(X)).cpu().numpy()
     assert O.linf_error(got, O.evaluate_expansion(prob.support, ch, X)) <= 1e-12 * np.abs(ch).sum()
     plan.close()
+
+
+@pytest.mark.parametrize("m", [1, 65, 700])
+def test_eval_support_slices(fct, m):
+    """Few points, long support: with the workspace the support is cut into
+    slices summed in order; without it one workgroup per 64 points sums it
+    all.  Both match the oracle; each is reproducible."""
+    prob = W.config2()
+    plan = fct.Plan(prob.support, prob.grids)
+    rng = np.random.default_rng(m)
+    c = rng.standard_normal(plan.n) * 2.0 ** (-prob.support.sum(axis=1) / 4.0)
+    X = rng.uniform(-1, 1, size=(m, prob.D))
+    ref = O.evaluate_expansion(prob.support, c, X)
+    tol = 1e-12 * np.sum(np.abs(c))
+    cd, xd = _dev(c), _dev(X)
+    sliced = plan.eval(cd, xd)
+    whole = plan.eval(cd, xd, ws=False)
+    assert O.linf_error(sliced.cpu().numpy(), ref) <= tol
+    assert O.linf_error(whole.cpu().numpy(), ref) <= tol
+    assert torch.equal(sliced, plan.eval(cd, xd))
+    assert torch.equal(whole, plan.eval(cd, xd, ws=False))
+    plan.close()
