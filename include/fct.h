@@ -279,6 +279,39 @@ fct_status fct_dct(const fct_plan* plan, const double* d_samples, double* d_b,
 fct_status fct_dct_full(const fct_plan* plan, const double* d_samples, double* d_out,
                         int32_t mode, fct_ws* ws, hipStream_t stream);
 
+/* ---- condition of A and the grid count (Sec. 3.3, Alg. 2) ---------------
+ * fct_plan_condition: extreme eigenvalues of A^T A by Lanczos from the start
+ * vector d_v0 (double [n], nonzero; the caller draws it, e.g. Gaussian) with
+ * full reorthogonalisation, on a single-problem plan.  Runs until
+ * max_steps steps (at most n), an invariant subspace (exact), or, with
+ * tol > 0, until both extreme Ritz values moved by at most tol * lambda_max
+ * over the last 8 steps (checked from step 16).  The Ritz values bound the
+ * spectrum from inside (lambda_min from above), so a short run can only
+ * under-state kappa.  full_rank = lambda_min > rank_tol * lambda_max;
+ * kappa = sqrt(lambda_max / lambda_min), HUGE_VAL when not full rank.
+ * Allocates (max_steps + 1) vectors of n doubles (FCT_EINVAL above 32 GiB);
+ * synchronous on `stream`.  Sums are in fixed order (reproducible).
+ * fct_select_grids: Alg. 2's loop.  For L = 1, 2, ... builds the plan of the
+ * first L candidate grids (host int32 [n_cand][D], drawn by the caller with
+ * Alg. 1; plan flag FCT_PLAN_ALLOW_RANK_DEFICIENT) and stops at the first L
+ * whose estimate is full rank with kappa <= kappa0: *out_L = L, out = its
+ * estimate.  FCT_ENOCONV with *out_L = 0 if no prefix qualifies. */
+typedef struct fct_cond_info {
+  double lambda_min;    /* smallest Ritz value of A^T A */
+  double lambda_max;    /* largest Ritz value of A^T A */
+  double kappa;         /* sqrt(lambda_max / lambda_min); HUGE_VAL if not full rank */
+  int32_t steps;        /* Lanczos steps taken */
+  int32_t full_rank;    /* lambda_min > rank_tol * lambda_max */
+} fct_cond_info;
+
+fct_status fct_plan_condition(const fct_plan* plan, const double* d_v0, int32_t max_steps,
+                              double tol, double rank_tol, hipStream_t stream,
+                              fct_cond_info* out);
+fct_status fct_select_grids(int32_t D, int64_t n_support, const int32_t* support,
+                            int32_t n_cand, const int32_t* candidates, double kappa0,
+                            const double* d_v0, int32_t max_steps, double tol, double rank_tol,
+                            hipStream_t stream, int32_t* out_L, fct_cond_info* out);
+
 /* ---- evaluation (Sec. 2: p(x) = sum over the support of c_n T_n(x)) ------
  * d_f[q] = sum_j d_c[j] prod_i T_{S[j][i]}(d_x[q * D + i]) for 0 <= q < m:
  * the expansion with coefficients d_c (double [n], the plan's support

@@ -45,7 +45,7 @@ __all__ = [
     "dense_A", "sparse_A", "lstsq_qr", "lstsq_normal", "rank_check",
     "gram_matrix", "normal_residual", "fct_solve", "max_rel_err", "lstsq_lsqr",
     "mean_l2_err", "fold_injective", "evaluate_expansion", "linf_error",
-    "function_values",
+    "function_values", "select_grid_count",
 ]
 
 
@@ -468,6 +468,18 @@ def rank_check(plan: Plan, kappa_max: float = 1e4):
     full = lmin > 1e-10 * lmax
     kappa = math.sqrt(lmax / lmin) if lmin > 0 else math.inf
     return bool(full and kappa <= kappa_max), kappa
+
+
+def select_grid_count(support, candidates, kappa_max: float = 1e4):
+    """Alg. 2: append the candidate grids (drawn by Alg. 1) one at a time and
+    stop at the first L whose stacked A is full rank with kappa(A) <=
+    kappa_max.  Returns (L, kappa), or (0, kappa of all candidates)."""
+    kappa = math.inf
+    for L in range(1, len(candidates) + 1):
+        ok, kappa = rank_check(build_plan(support, np.asarray(candidates)[:L]), kappa_max)
+        if ok:
+            return L, kappa
+    return 0, kappa
 
 
 def normal_residual(plan: Plan, b: np.ndarray, c: np.ndarray) -> np.ndarray:

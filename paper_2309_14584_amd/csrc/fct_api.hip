@@ -907,6 +907,165 @@ fct_status fct_eval(const fct_plan* p, const double* d_c, int64_t m, const doubl
   return FCT_OK;
 }
 
+// ---- condition estimate and grid-count selection (Alg. 2) ---------------
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a[0..k) and off-diagonal b[0..k-1) (Sturm sequence of the LDL^T
+// pivots).
+static int sturm_count(const std::vector<double>& a, const std::vector<double>& b, int k,
+                       double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    d = (a[i] - x) - (i > 0 ? off / d : 0.0);
+    if (d == 0.0) d = -1e-300;            // a zero pivot counts as negative
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// The idx-th smallest eigenvalue (0-based) of the tridiagonal, by bisection
+// inside its Gershgorin interval.
+static double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k,
+                          int idx) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 400 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, k, mid) > idx) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Lanczos on A^T A from d_v0 with full reorthogonalisation (two classical
+// Gram-Schmidt passes against every earlier vector), on `s`, synchronous.
+static fct_status lanczos_condition(const fct_plan* p, const double* d_v0, int32_t max_steps,
+                                    double tol, double rank_tol, hipStream_t s,
+                                    fct_cond_info* out) {
+  const int64_t n = p->n;
+  const int kmax = (int)std::max<int64_t>(1, std::min<int64_t>(max_steps, n));
+  if ((double)(kmax + 1) * (double)n * 8.0 > 32.0 * (1ull << 30)) {
+    set_error("condition estimate: %d steps of %lld-vectors exceed 32 GiB", kmax,
+              (long long)n);
+    return FCT_EINVAL;
+  }
+  double *V = nullptr, *w = nullptr, *q = nullptr, *part = nullptr, *h = nullptr;
+  struct G {
+    double** v[5];
+    ~G() { for (auto x : v) dfree(*x); }
+  } guard{{&V, &w, &q, &part, &h}};
+  const int64_t ldp = kmax + 1;
+  FCT_HIP(dalloc(&V, (int64_t)(kmax + 1) * n, nullptr));
+  FCT_HIP(dalloc(&w, n, nullptr));
+  FCT_HIP(dalloc(&q, std::max<int64_t>(p->M, 1), nullptr));
+  FCT_HIP(dalloc(&part, (int64_t)cond_dot_blocks(n) * ldp, nullptr));
+  FCT_HIP(dalloc(&h, ldp, nullptr));
+  std::vector<double> hh((size_t)ldp), alpha, beta;
+  // v_1 = v0 / ||v0||
+  FCT_HIP(launch_multi_dot(d_v0, n, 1, d_v0, n, part, ldp, h, s));
+  FCT_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double), hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipStreamSynchronize(s));
+  if (!(hh[0] > 0.0) || !std::isfinite(hh[0])) {
+    set_error("condition estimate: the start vector is zero or not finite");
+    return FCT_EINVAL;
+  }
+  FCT_HIP(launch_scale(d_v0, 1.0 / std::sqrt(hh[0]), V, n, s));
+  double lmin = 0.0, lmax = 0.0, lmin_prev = 0.0, lmax_prev = 0.0;
+  int steps = 0;
+  for (int j = 0; j < kmax; ++j) {
+    const double* vj = V + (int64_t)j * n;
+    FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, vj, q, s));
+    FCT_HIP(launch_apply_AT(p->d_cblk, p->ncblk, p->d_rowmap, q, w, s));
+    double a = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      FCT_HIP(launch_multi_dot(V, n, j + 1, w, n, part, ldp, h, s));
+      FCT_HIP(launch_orth_update(V, n, j + 1, h, w, n, s));
+      FCT_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipStreamSynchronize(s));
+      a += hh[(size_t)j];
+    }
+    FCT_HIP(launch_multi_dot(w, n, 1, w, n, part, ldp, h, s));
+    FCT_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double), hipMemcpyDeviceToHost, s));
+    FCT_HIP(hipStreamSynchronize(s));
+    const double bn = std::sqrt(std::max(hh[0], 0.0));
+    alpha.push_back(a);
+    steps = j + 1;
+    const bool check = steps % 8 == 0 || steps == kmax;
+    const double scale = std::max(lmax, std::fabs(a));
+    const bool breakdown = !(bn > 1e-13 * std::max(scale, 1e-300)) || steps == n;
+    if (check || breakdown) {
+      lmin = tridiag_eig(alpha, beta, steps, 0);
+      lmax = tridiag_eig(alpha, beta, steps, steps - 1);
+      if (breakdown) break;               // T is A^T A on an invariant subspace
+      if (tol > 0.0 && steps >= 16 && std::fabs(lmin - lmin_prev) <= tol * lmax &&
+          std::fabs(lmax - lmax_prev) <= tol * lmax)
+        break;
+      lmin_prev = lmin;
+      lmax_prev = lmax;
+    }
+    if (steps == kmax) break;
+    beta.push_back(bn);
+    FCT_HIP(launch_scale(w, 1.0 / bn, V + (int64_t)(j + 1) * n, n, s));
+  }
+  fct_cond_info info;
+  std::memset(&info, 0, sizeof(info));
+  info.lambda_min = lmin;
+  info.lambda_max = lmax;
+  info.steps = steps;
+  info.full_rank = lmin > rank_tol * lmax ? 1 : 0;
+  info.kappa = (info.full_rank && lmin > 0.0) ? std::sqrt(lmax / lmin) : HUGE_VAL;
+  if (out) *out = info;
+  return FCT_OK;
+}
+
+fct_status fct_plan_condition(const fct_plan* p, const double* d_v0, int32_t max_steps,
+                              double tol, double rank_tol, hipStream_t s, fct_cond_info* out) {
+  if (!p || !d_v0) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  if (p->nprob != 1) { set_error("condition estimate needs a single-problem plan"); return FCT_EINVAL; }
+  if (max_steps < 1 || !(tol >= 0.0) || !(rank_tol >= 0.0)) {
+    set_error("bad max_steps %d, tol or rank_tol", max_steps);
+    return FCT_EINVAL;
+  }
+  return lanczos_condition(p, d_v0, max_steps, tol, rank_tol, s, out);
+}
+
+fct_status fct_select_grids(int32_t D, int64_t n, const int32_t* support, int32_t n_cand,
+                            const int32_t* candidates, double kappa0, const double* d_v0,
+                            int32_t max_steps, double tol, double rank_tol, hipStream_t s,
+                            int32_t* out_L, fct_cond_info* out) {
+  if (!out_L || !candidates || !support || !d_v0 || n_cand < 1 || !(kappa0 >= 1.0)) {
+    set_error("bad argument to fct_select_grids");
+    return FCT_EINVAL;
+  }
+  *out_L = 0;
+  fct_cond_info info;
+  std::memset(&info, 0, sizeof(info));
+  for (int32_t L = 1; L <= n_cand; ++L) {
+    fct_plan* p = nullptr;
+    fct_status st = fct_plan_create(D, n, support, L, candidates, FCT_PLAN_ALLOW_RANK_DEFICIENT,
+                                    s, &p);
+    if (st != FCT_OK) return st;
+    st = fct_plan_condition(p, d_v0, max_steps, tol, rank_tol, s, &info);
+    fct_plan_destroy(p);
+    if (st != FCT_OK) return st;
+    if (info.full_rank && info.kappa <= kappa0) {
+      *out_L = L;
+      if (out) *out = info;
+      return FCT_OK;
+    }
+  }
+  if (out) *out = info;
+  set_error("no prefix of the %d candidate grids reaches kappa <= %g", n_cand, kappa0);
+  return FCT_ENOCONV;
+}
+
 fct_status fct_apply_A(const fct_plan* p, const double* d_c, double* d_q, hipStream_t s) {
   if (!p || !d_c || !d_q) { set_error("NULL argument"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;

@@ -138,6 +138,16 @@ hipError_t launch_eval(const int32_t* support, const double* c, int64_t n, int D
                        int64_t m, const double* X, double* f, int slices, double* scratch,
                        hipStream_t s);
 
+// condition estimate (Lanczos on A^T A): part holds cond_dot_blocks(n) x ldp
+// doubles; out[i] = sum_e X[i][e] w[e] for i < cnt (cnt <= ldp)
+int cond_dot_blocks(int64_t n);
+hipError_t launch_multi_dot(const double* X, int64_t ld, int cnt, const double* w, int64_t n,
+                            double* part, int64_t ldp, double* out, hipStream_t s);
+// w -= sum_{i < cnt} X[i] h[i]
+hipError_t launch_orth_update(const double* X, int64_t ld, int cnt, const double* h, double* w,
+                              int64_t n, hipStream_t s);
+hipError_t launch_scale(const double* x, double a, double* y, int64_t n, hipStream_t s);
+
 // Work decomposition of the CGLS kernels.  A plan holds one or more
 // independent problems (a batch); every workgroup of the row (column)
 // kernel covers up to kBlock rows (columns) of a single problem.

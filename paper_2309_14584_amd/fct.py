@@ -60,6 +60,11 @@ class SolveInfo(ctypes.Structure):
                 ("refinements", _i32), ("reserved", _i32)]
 
 
+class CondInfo(ctypes.Structure):
+    _fields_ = [("lambda_min", _dbl), ("lambda_max", _dbl), ("kappa", _dbl),
+                ("steps", _i32), ("full_rank", _i32)]
+
+
 class TuneInfo(ctypes.Structure):
     _fields_ = [("dct_tile", _i32), ("unit_rows", _i32), ("dct_us", _dbl * 3),
                 ("rows_us", _dbl * 4), ("dct_engine", _i32), ("reserved", _i32),
@@ -98,6 +103,10 @@ _ws_problem_info = _sig("fct_ws_problem_info", ctypes.c_int, _vp, _i32, ctypes.P
 _plan_tune = _sig("fct_plan_tune", ctypes.c_int, _vp, _vp, _i32, _vp, ctypes.POINTER(TuneInfo))
 _plan_set_dct_engine = _sig("fct_plan_set_dct_engine", ctypes.c_int, _vp, _i32, _i32)
 _eval = _sig("fct_eval", ctypes.c_int, _vp, _vp, _i64, _vp, _vp, _vp, _vp)
+_plan_condition = _sig("fct_plan_condition", ctypes.c_int, _vp, _vp, _i32, _dbl, _dbl, _vp,
+                       ctypes.POINTER(CondInfo))
+_select_grids = _sig("fct_select_grids", ctypes.c_int, _i32, _i64, _vp, _i32, _vp, _dbl, _vp,
+                     _i32, _dbl, _dbl, _vp, ctypes.POINTER(_i32), ctypes.POINTER(CondInfo))
 _solve = _sig("fct_solve", ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
               ctypes.POINTER(SolveInfo), _vp, _vp)
 
@@ -106,7 +115,33 @@ EXPORTED = ["fct_last_error", "fct_status_string", "fct_abi_version", "fct_plan_
             "fct_grid_nodes", "fct_ws_create", "fct_ws_destroy", "fct_sample", "fct_dct",
             "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve", "fct_batch_create",
             "fct_plan_problem", "fct_ws_problem_info", "fct_plan_tune",
-            "fct_plan_set_dct_engine", "fct_eval"]
+            "fct_plan_set_dct_engine", "fct_eval", "fct_plan_condition", "fct_select_grids"]
+
+
+def _cond_dict(info):
+    return {"lambda_min": info.lambda_min, "lambda_max": info.lambda_max, "kappa": info.kappa,
+            "steps": info.steps, "full_rank": bool(info.full_rank)}
+
+
+def select_grids(support, candidates, kappa0, v0, max_steps=200, tol=1e-10, rank_tol=1e-10,
+                 stream=None):
+    """Alg. 2 on the GPU (fct_select_grids): the first L such that the plan
+    of candidates[:L] is full rank with kappa(A) <= kappa0.  support int32
+    [n, D], candidates int32 [n_cand, D] (host), v0 device double [n].
+    Returns (L, estimate dict); L = 0 if no prefix qualifies."""
+    torch = _torch()
+    S = np.ascontiguousarray(support, dtype=np.int32)
+    C = np.ascontiguousarray(candidates, dtype=np.int32)
+    n, D = S.shape
+    L = _i32(0)
+    info = CondInfo()
+    st = _select_grids(D, n, S.ctypes.data_as(_vp), C.shape[0], C.ctypes.data_as(_vp),
+                       float(kappa0), _ptr(v0, torch.float64, n, "v0"), int(max_steps),
+                       float(tol), float(rank_tol), _stream(stream), ctypes.byref(L),
+                       ctypes.byref(info))
+    if st not in (FCT_OK, FCT_ENOCONV):
+        _check(st)
+    return L.value, _cond_dict(info)
 
 
 class FctError(RuntimeError):
@@ -364,6 +399,15 @@ class Plan:
                      _ptr(out, torch.float64, m, "out"),
                      None if ws is False else self._wsh(ws), _stream(stream)))
         return out
+
+    def condition(self, v0, max_steps=200, tol=1e-10, rank_tol=1e-10, stream=None):
+        """Extreme eigenvalues of A^T A and kappa(A) by Lanczos from the
+        device vector v0 (fct_plan_condition); returns a dict."""
+        torch = _torch()
+        info = CondInfo()
+        _check(_plan_condition(self._h, _ptr(v0, torch.float64, self.n, "v0"), int(max_steps),
+                               float(tol), float(rank_tol), _stream(stream), ctypes.byref(info)))
+        return _cond_dict(info)
 
     def apply_A(self, c, out=None, stream=None):
         torch = _torch()

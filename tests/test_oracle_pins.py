@@ -563,3 +563,28 @@ def test_euclidean_workload_recovers_planted():
     assert full and kappa < 1e2
     c, _, _ = O.fct_solve(prob.support, prob.grids, O.sample_problem(prob), "qr")
     assert O.max_rel_err(c, prob.coeffs) < 1e-12
+
+
+def test_rank_check_kappa_is_the_svd_condition_number():
+    """kappa(A) from the Gram matrix's eigenvalues equals LAPACK's SVD
+    condition number of the dense A (numpy.linalg.cond)."""
+    for prob in [W.config1(), W.small_problem(3, 3, 5, 2, 6, 4), W.euclidean_problem()]:
+        plan = O.build_plan(prob.support, prob.grids)
+        full, kappa = O.rank_check(plan)
+        assert full
+        assert abs(kappa / np.linalg.cond(O.dense_A(plan)) - 1.0) < 1e-8
+
+
+def test_select_grid_count_is_the_first_qualifying_prefix():
+    """Alg. 2 on explicit candidates: the returned L qualifies and L - 1 does
+    not, checked with SVD ranks and condition numbers of the dense A."""
+    S = W.total_degree_support(3, 5)
+    cands = np.random.default_rng(59).integers(1, 6, size=(12, 3)).astype(np.int32)
+    L, kappa = O.select_grid_count(S, cands, 1e4)
+    assert L >= 2
+
+    def svd_ok(k):
+        A = O.dense_A(O.build_plan(S, cands[:k]))
+        sv = np.linalg.svd(A, compute_uv=False)
+        return sv[-1] > 1e-5 * sv[0] and sv[0] / sv[-1] <= 1e4
+    assert svd_ok(L) and not svd_ok(L - 1)
