@@ -22,23 +22,25 @@ __device__ __forceinline__ double cond_block_sum(double v, double* sh) {
   return r;
 }
 
-// part[b * ldp + i] = sum over this workgroup's elements of X[i][e] * w[e],
-// for rows i < cnt (row stride ld); elements e = b*kBlock + t, then strided
-// by gridDim.x * kBlock.
+// part[b * ldp + i] = sum over workgroup b's slice of elements of
+// X[i][e] * w[e], for rows i < cnt (row stride ld).  Workgroup b owns the
+// contiguous slice [b * len, (b + 1) * len); wave w takes rows i = w (mod 4)
+// and reduces each row with a butterfly (no barriers).
 __global__ __launch_bounds__(kBlock) void multi_dot_kernel(const double* __restrict__ X,
                                                            int64_t ld, int cnt,
                                                            const double* __restrict__ w,
                                                            int64_t n, double* __restrict__ part,
                                                            int64_t ldp) {
-  __shared__ double sh[kBlock / 64];
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int i = 0; i < cnt; ++i) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t len = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t e0 = (int64_t)blockIdx.x * len;
+  const int64_t e1 = min(n, e0 + len);
+  for (int i = wave; i < cnt; i += kBlock / 64) {
     const double* xi = X + (int64_t)i * ld;
     double acc = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride)
-      acc = fma(xi[e], w[e], acc);
-    const double s = cond_block_sum(acc, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + i] = s;
+    for (int64_t e = e0 + lane; e < e1; e += 64) acc = fma(xi[e], w[e], acc);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) part[(int64_t)blockIdx.x * ldp + i] = acc;
   }
 }
 

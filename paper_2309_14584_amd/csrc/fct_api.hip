@@ -955,17 +955,18 @@ static fct_status lanczos_condition(const fct_plan* p, const double* d_v0, int32
               (long long)n);
     return FCT_EINVAL;
   }
-  double *V = nullptr, *w = nullptr, *q = nullptr, *part = nullptr, *h = nullptr;
+  double *V = nullptr, *w = nullptr, *q = nullptr, *part = nullptr, *h = nullptr, *ab = nullptr;
   struct G {
-    double** v[5];
+    double** v[6];
     ~G() { for (auto x : v) dfree(*x); }
-  } guard{{&V, &w, &q, &part, &h}};
+  } guard{{&V, &w, &q, &part, &h, &ab}};
   const int64_t ldp = kmax + 1;
   FCT_HIP(dalloc(&V, (int64_t)(kmax + 1) * n, nullptr));
   FCT_HIP(dalloc(&w, n, nullptr));
   FCT_HIP(dalloc(&q, std::max<int64_t>(p->M, 1), nullptr));
   FCT_HIP(dalloc(&part, (int64_t)cond_dot_blocks(n) * ldp, nullptr));
   FCT_HIP(dalloc(&h, ldp, nullptr));
+  FCT_HIP(dalloc(&ab, 3, nullptr));      // per step: the two passes' h[j], ||w||^2
   std::vector<double> hh((size_t)ldp), alpha, beta;
   // v_1 = v0 / ||v0||
   FCT_HIP(launch_multi_dot(d_v0, n, 1, d_v0, n, part, ldp, h, s));
@@ -982,18 +983,16 @@ static fct_status lanczos_condition(const fct_plan* p, const double* d_v0, int32
     const double* vj = V + (int64_t)j * n;
     FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, vj, q, s));
     FCT_HIP(launch_apply_AT(p->d_cblk, p->ncblk, p->d_rowmap, q, w, s));
-    double a = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       FCT_HIP(launch_multi_dot(V, n, j + 1, w, n, part, ldp, h, s));
       FCT_HIP(launch_orth_update(V, n, j + 1, h, w, n, s));
-      FCT_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipStreamSynchronize(s));
-      a += hh[(size_t)j];
+      FCT_HIP(hipMemcpyAsync(ab + pass, h + j, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    FCT_HIP(launch_multi_dot(w, n, 1, w, n, part, ldp, h, s));
-    FCT_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double), hipMemcpyDeviceToHost, s));
+    FCT_HIP(launch_multi_dot(w, n, 1, w, n, part, ldp, ab + 2, s));
+    FCT_HIP(hipMemcpyAsync(hh.data(), ab, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     FCT_HIP(hipStreamSynchronize(s));
-    const double bn = std::sqrt(std::max(hh[0], 0.0));
+    const double a = hh[0] + hh[1];
+    const double bn = std::sqrt(std::max(hh[2], 0.0));
     alpha.push_back(a);
     steps = j + 1;
     const bool check = steps % 8 == 0 || steps == kmax;

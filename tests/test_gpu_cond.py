@@ -32,7 +32,7 @@ def _exact(plan):
     return ev[0], ev[-1]
 
 
-SMALL = [W.config1(), W.small_problem(3, 3, 5, 2, 6, 4), W.small_problem(4, 4, 6, 1, 7, 3),
+SMALL = [W.config1(), W.small_problem(3, 3, 5, 2, 6, 4), W.small_problem(6, 4, 5, 3, 7, 4),
          W.euclidean_problem()]
 
 
