@@ -263,6 +263,22 @@ def bench_precision(fct, torch, steps):
     return res
 
 
+def bench_grid_selection(fct, torch, prob):
+    """Alg. 2 on the GPU for the D=6 workload's support: candidate grids
+    N_i ~ U{4..8} (the workload's grid law) are appended until the Lanczos
+    estimate of kappa(A) is <= 1e4; timed end to end (plan builds included)."""
+    cands = np.random.default_rng(21).integers(4, 9, size=(16, prob.D)).astype(np.int32)
+    v0 = torch.tensor(np.random.default_rng(22).standard_normal(prob.n), dtype=torch.float64,
+                      device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, est = fct.select_grids(prob.support, cands, 1e4, v0, max_steps=400, tol=1e-10)
+    torch.cuda.synchronize()
+    return {"workload": f"{prob.name} support, candidates N_i ~ U{{4..8}}, kappa_0 = 1e4",
+            "grids": L, "kappa": est["kappa"], "lanczos_steps": est["steps"],
+            "seconds": time.perf_counter() - t0}
+
+
 def bench_serving(fct, torch, duration, rate=200.0, slots=4):
     """The serving workload: requests drawn (seeded) from a pool of 64 jobs
     of four kinds (D2 |n|_1<=16; D6 |n|_1<=12 exp-cos; a batched-workload
@@ -451,6 +467,7 @@ def main():
                        "max_abs_f": float(np.max(np.abs(fx))), "eval_ms": 1e3 * t_eval,
                        "eval_terms_per_s": 5000 * prob.n / t_eval}
     plan.close()
+    out["grid_selection"] = bench_grid_selection(fct, torch, prob)
     if not args.skip_batched:
         out["batched"] = bench_batched(fct, torch, args.batched_steps,
                                        args.batched_modes.split(","))
