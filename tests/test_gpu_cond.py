@@ -32,8 +32,7 @@ def _exact(plan):
     return ev[0], ev[-1]
 
 
-SMALL = [W.config1(), W.small_problem(3, 3, 5, 2, 6, 4), W.small_problem(6, 4, 5, 3, 7, 4),
-         W.euclidean_problem()]
+SMALL = [W.config1(), W.small_problem(3, 3, 5, 2, 6, 4), W.small_problem(6, 4, 5, 3, 7, 4)]
 
 
 @pytest.mark.parametrize("prob", SMALL, ids=[p.name for p in SMALL])
@@ -80,7 +79,7 @@ def test_condition_of_the_d6_workload(fct):
 SELECT = [("D3_d5", W.total_degree_support(3, 5), 59, 1, 6),
           ("D4_d6", W.total_degree_support(4, 6), 61, 1, 7),
           ("D2_d16", W.total_degree_support(2, 16), 63, 6, 20),
-          ("euclid_D5_r6", W.euclidean_degree_support(5, 6.0), 11, 2, 6)]
+          ("euclid_D4_r5", W.euclidean_degree_support(4, 5.0), 17, 2, 5)]
 
 
 @pytest.mark.parametrize("name,S,seed,lo,hi", SELECT, ids=[c[0] for c in SELECT])
