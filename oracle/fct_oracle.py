@@ -33,6 +33,7 @@ Cholesky solves, and scipy.sparse products.
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
@@ -45,7 +46,7 @@ __all__ = [
     "dense_A", "sparse_A", "lstsq_qr", "lstsq_normal", "rank_check",
     "gram_matrix", "normal_residual", "fct_solve", "max_rel_err", "lstsq_lsqr",
     "mean_l2_err", "fold_injective", "evaluate_expansion", "linf_error",
-    "function_values", "select_grid_count",
+    "function_values", "select_grid_count", "dct_entries",
 ]
 
 
@@ -182,6 +183,50 @@ def dct_grid(samples: np.ndarray, grid) -> np.ndarray:
     for axis, N in enumerate(grid):
         t = dct_axis(t, axis, dct1_matrix(N))
     return t.reshape(-1)
+
+
+def dct_entries(family: int, params, grid, multis, slab_points: int = 1 << 21):
+    """Selected entries of the D-dimensional DCT-I of f sampled on one grid
+    (eq. multi_dim_dct), each by its definition
+        a_m = sum_k f(x_k) prod_i C_{N_i}[m_i, k_i],
+    without forming the transformed tensor.  The leading axes 0..s-1 (s the
+    fewest such that a slab of the trailing axes holds at most slab_points
+    points) index slabs; every slab is sampled, contracted with the rows
+    C_{N_i}[m_i] of the trailing axes, and weighted by the product of
+    C_{N_i}[m_i, k_i] over the leading axes.  Also returns the same sums of
+    absolute values (|f|, |C|), the scale of the rounding error of any
+    evaluation order.  multis: int [r][D].  Returns (values [r], abs_sums [r])."""
+    grid = [int(v) for v in grid]
+    D = len(grid)
+    ext = [N + 1 for N in grid]
+    mats = [dct1_matrix(N) for N in grid]
+    multis = np.asarray(multis, dtype=np.int64)
+    s = 0
+    while s < D and int(np.prod(ext[s:], dtype=np.int64)) > slab_points:
+        s += 1
+    rest = int(np.prod(ext[s:], dtype=np.int64))
+    vals = np.zeros(len(multis))
+    abss = np.zeros(len(multis))
+    for lead in itertools.product(*[range(e) for e in ext[:s]]):
+        flat = 0
+        for i in range(s):
+            flat = flat * ext[i] + lead[i]
+        X = grid_coordinates(grid, flat * rest, (flat + 1) * rest)
+        f = _function_at(family, params, X).reshape(ext[s:])
+        for r, m in enumerate(multis):
+            w = 1.0
+            for i in range(s):
+                w *= mats[i][m[i], lead[i]]
+            if w == 0.0:
+                continue
+            t, ta = f, np.abs(f)
+            for i in range(s, D):                 # contract the trailing axes in order
+                row = mats[i][m[i]]
+                t = np.tensordot(t, row, axes=([0], [0]))
+                ta = np.tensordot(ta, np.abs(row), axes=([0], [0]))
+            vals[r] += w * float(t)
+            abss[r] += abs(w) * float(ta)
+    return vals, abss
 
 
 def idct_grid(coef: np.ndarray, grid) -> np.ndarray:

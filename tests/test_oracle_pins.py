@@ -588,3 +588,19 @@ def test_select_grid_count_is_the_first_qualifying_prefix():
         sv = np.linalg.svd(A, compute_uv=False)
         return sv[-1] > 1e-5 * sv[0] and sv[0] / sv[-1] <= 1e4
     assert svd_ok(L) and not svd_ok(L - 1)
+
+
+def test_dct_entries_equal_the_full_transform():
+    """Single DCT-I entries by slab-wise contraction equal the entries of the
+    whole transform (dct_grid, itself pinned to scipy's DCT-I)."""
+    grid = [3, 4, 2, 5]
+    prm = np.concatenate([[0.8], np.random.default_rng(61).uniform(-.5, .5, 4)])
+    full = O.dct_grid(O.sample_function(W.FAMILY_GAUSS, prm, grid), grid).reshape(
+        [N + 1 for N in grid])
+    ms = np.array([[0, 0, 0, 0], [3, 4, 2, 5], [1, 2, 0, 3], [2, 0, 1, 4]])
+    vals, abss = O.dct_entries(W.FAMILY_GAUSS, prm, grid, ms, slab_points=64)
+    for v, a, m in zip(vals, abss, ms):
+        assert abs(v - full[tuple(m)]) <= 1e-14 * a
+        assert a >= abs(v)
+    whole, _ = O.dct_entries(W.FAMILY_GAUSS, prm, grid, ms)        # one slab
+    assert np.allclose(whole, vals, rtol=0, atol=1e-14 * np.max(abss))
