@@ -46,7 +46,7 @@ __all__ = [
     "dense_A", "sparse_A", "lstsq_qr", "lstsq_normal", "rank_check",
     "gram_matrix", "normal_residual", "fct_solve", "max_rel_err", "lstsq_lsqr",
     "mean_l2_err", "fold_injective", "evaluate_expansion", "linf_error",
-    "function_values", "select_grid_count", "dct_entries",
+    "function_values", "select_grid_count", "dct_entries", "grid_coordinates",
 ]
 
 
