@@ -54,7 +54,7 @@ extern "C" {
 #endif
 
 #define FCT_ABI_VERSION 2
-#define FCT_MAX_DIM 64       /* largest D accepted */
+#define FCT_MAX_DIM 128      /* largest D accepted */
 #define FCT_MAX_DEGREE 63    /* largest Lobatto degree N_i (64 nodes) */
 
 typedef enum fct_status {

@@ -177,7 +177,9 @@ def dct_grid(samples: np.ndarray, grid) -> np.ndarray:
     ``samples`` is the flat row-major tensor (last dimension fastest) of
     shape (N_1+1, ..., N_D+1); the result has the same layout.
     """
-    grid = [int(v) for v in grid]
+    # single-node axes (N = 0) carry the 1x1 identity and do not change the
+    # flat row-major layout, so the tensor is formed over the other axes only
+    grid = [int(v) for v in grid if int(v) > 0]
     shape = tuple(v + 1 for v in grid)
     t = np.asarray(samples, dtype=np.float64).reshape(shape)
     for axis, N in enumerate(grid):
@@ -231,7 +233,7 @@ def dct_entries(family: int, params, grid, multis, slab_points: int = 1 << 21):
 
 def idct_grid(coef: np.ndarray, grid) -> np.ndarray:
     """Evaluate a coefficient tensor on the grid (inverse of dct_grid)."""
-    grid = [int(v) for v in grid]
+    grid = [int(v) for v in grid if int(v) > 0]    # single-node axes: identity
     shape = tuple(v + 1 for v in grid)
     t = np.asarray(coef, dtype=np.float64).reshape(shape)
     for axis, N in enumerate(grid):
@@ -367,14 +369,16 @@ def sample_planted(support, coeffs, grid) -> np.ndarray:
     """
     S = np.asarray(support, dtype=np.int64)
     grid = [int(v) for v in grid]
-    D = len(grid)
     nmax = int(S.max()) if S.size else 0
-    tables = [cheb_T_recurrence(nmax, lobatto_nodes(N)) for N in grid]
-    shape = tuple(N + 1 for N in grid)
+    # a single-node axis (N = 0, node x = 1) contributes T_n(1) = 1 to every
+    # term and no axis to the flat layout; the tensor spans the other axes
+    axes = [i for i, N in enumerate(grid) if N > 0]
+    tables = {i: cheb_T_recurrence(nmax, lobatto_nodes(grid[i])) for i in axes}
+    shape = tuple(grid[i] + 1 for i in axes)
     out = np.zeros(shape)
     for j in range(S.shape[0]):
         term = np.asarray(coeffs[j], dtype=np.float64)
-        for i in range(D):
+        for i in axes:
             vec = tables[i][S[j, i]]
             term = np.multiply.outer(term, vec)
         out += term

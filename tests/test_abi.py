@@ -55,8 +55,8 @@ def test_host_validation_errors(fct):
     st, msg, _ = _create(fct, np.array([[0, 0], [1, 0], [1, 0]]), np.array([[3, 3]]))
     assert st == fct.FCT_EINVAL and "equal" in msg
     assert _create(fct, np.array([[0, -1]]), np.array([[3, 3]]))[0] == fct.FCT_EINVAL
-    st, msg, _ = _create(fct, np.zeros((1, 65)), np.zeros((1, 65)))
-    assert st == fct.FCT_EINVAL and "D=65" in msg
+    st, msg, _ = _create(fct, np.zeros((1, 129)), np.zeros((1, 129)))
+    assert st == fct.FCT_EINVAL and "D=129" in msg
 
 
 def test_rank_precheck(fct):

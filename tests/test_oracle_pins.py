@@ -604,3 +604,32 @@ def test_dct_entries_equal_the_full_transform():
         assert a >= abs(v)
     whole, _ = O.dct_entries(W.FAMILY_GAUSS, prm, grid, ms)        # one slab
     assert np.allclose(whole, vals, rtol=0, atol=1e-14 * np.max(abss))
+
+
+def test_single_node_axes_dropped_from_tensors():
+    """Samples and transforms on a grid with single-node axes (N = 0, the
+    node x = 1) equal the expansion evaluated at the nodes and the DCT taken
+    over every axis of the full-rank tensor."""
+    rng = np.random.default_rng(67)
+    S = W.total_degree_support(5, 3)
+    c = rng.standard_normal(S.shape[0])
+    grid = [3, 0, 2, 0, 1]
+    X = np.stack(np.meshgrid(*[O.lobatto_nodes(N) for N in grid], indexing="ij"),
+                 axis=-1).reshape(-1, 5)
+    smp = O.sample_planted(S, c, grid)
+    assert np.max(np.abs(smp - O.evaluate_expansion(S, c, X))) < 1e-13 * np.abs(c).sum()
+    t = smp.reshape([N + 1 for N in grid])
+    for axis, N in enumerate(grid):
+        t = O.dct_axis(t, axis, O.dct1_matrix(N))
+    assert np.allclose(O.dct_grid(smp, grid), t.reshape(-1), rtol=0, atol=1e-15)
+
+
+@pytest.mark.slow
+def test_f3_sparse_support_recovers_exactly():
+    """The paper's f3 family in D = 100 (N = 2000 random multi-indices of
+    S^inf_{8,100}, 20 Alg.-1 grids): the oracle recovers the planted
+    coefficients (so A has full column rank)."""
+    p = W.f3_problem(2000)
+    assert p.D == 100 and len(np.unique(p.support, axis=0)) == p.n
+    c, plan, _ = O.fct_solve(p.support, p.grids, O.sample_problem(p), "auto")
+    assert O.max_rel_err(c, p.coeffs) < 1e-12

@@ -277,6 +277,37 @@ def euclidean_problem(seed: int = 11, family: int = FAMILY_PLANTED) -> Problem:
     return Problem(f"euclid_D5_r6_s{seed}_f{family}", S, grids, family, params, c, seed)
 
 
+def sparse_support(rng, D: int, d: int, N: int) -> np.ndarray:
+    """N random multi-indices of S^inf_{d,D} (every coordinate uniform in
+    0..d), the sparse supports of the paper's f3 family (Sec. 4).  Rows are
+    drawn independently; a repeated row (probability about N^2 / (2 (d+1)^D),
+    zero in practice for D = 100) is replaced by a fresh draw."""
+    S = rng.integers(0, d + 1, size=(N, D), dtype=np.int32)
+    if N * N < 2 * float(d + 1) ** D * 1e-6:
+        return np.ascontiguousarray(S)
+    while True:
+        _, first = np.unique(S, axis=0, return_index=True)
+        if len(first) == N:
+            return np.ascontiguousarray(S)
+        dup = np.setdiff1d(np.arange(N), first)
+        S[dup] = rng.integers(0, d + 1, size=(len(dup), D), dtype=np.int32)
+
+
+def f3_problem(N: int, seed: int = 5, D: int = 100, d: int = 8, K: int = 20) -> Problem:
+    """The paper's f3 family (Sec. 4): N random multi-indices of S^inf_{d,D},
+    coefficients uniform in [-1, 1], on K grids drawn by Alg. 1 (dimensions in
+    random order, degrees U{0..d} -- 1..d+1 nodes --, single nodes once the
+    running point count exceeds N).  K = 20 recovers the planted
+    coefficients exactly at every N tried (the oracle's LSQR check on the
+    small instance; the GPU's exact recovery on the large ones)."""
+    g_grid, g_coef, _ = streams(seed)
+    S = sparse_support(g_coef, D, d, N)
+    c = g_coef.uniform(-1.0, 1.0, size=N)
+    grids = np.ascontiguousarray(np.array([draw_grid_capped(g_grid, D, 0, d, N, 0)
+                                           for _ in range(K)], dtype=np.int32))
+    return Problem(f"f3_D{D}_d{d}_N{N}_K{K}", S, grids, FAMILY_PLANTED, np.zeros(0), c, seed)
+
+
 def config3_problem(rng_grid, rng_coef, cap=50_000):
     """One problem of the batched workload: D ~ U{3..8}, d ~ U{6..16}, d
     lowered until C(D+d, d) <= cap; grids drawn as in Alg. 1 (dimensions in
