@@ -279,6 +279,48 @@ def bench_grid_selection(fct, torch, prob):
             "seconds": time.perf_counter() - t0}
 
 
+def bench_sparse(fct, torch, sizes=(1_000_000, 10_000_000), steps=2):
+    """The paper's f3 family (sparse supports, Sec. 4): D = 100, N random
+    multi-indices of S^inf_{8,100}, 20 Alg.-1 grids, planted coefficients in
+    [-1, 1].  One step = sample (inverse DCT of the planted expansion) ->
+    DCT -> FP64 solve; the plan (Alg. 3's precomputation) is timed apart.
+    The paper reports N = 10^7 recovered in about 10 s on one CPU core."""
+    import workloads as W
+    out = []
+    for N in sizes:
+        p = W.f3_problem(N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = fct.Plan(p.support, p.grids, allow_rank_deficient=True)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        ct = torch.tensor(p.coeffs, dtype=torch.float64, device="cuda")
+        smp = torch.empty(plan.P, dtype=torch.float64, device="cuda")
+        b = torch.empty(plan.M, dtype=torch.float64, device="cuda")
+        c = torch.empty(plan.n, dtype=torch.float64, device="cuda")
+
+        def step():
+            plan.sample(fct.FAMILY_PLANTED, coeffs=ct, out=smp)
+            plan.dct(smp, out=b)
+            return plan.solve(b, out=c)[1]
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        err = float(np.max(np.abs(c.cpu().numpy() - p.coeffs)) / np.max(np.abs(p.coeffs)))
+        out.append({"D": p.D, "N": N, "grids": p.K, "points": plan.P, "rows": plan.M,
+                    "plan_seconds": t_plan, "ms_per_step": 1e3 * dt,
+                    "iterations": info.iterations, "max_rel_err": err,
+                    "recovered_coeffs_per_s": N / dt if err <= TOL else 0.0})
+        plan.close()
+        del p, ct, smp, b, c
+    return {"workload": "f3: D=100, random S^inf_{8,100} supports, 20 Alg.-1 grids, planted",
+            "runs": out}
+
+
 def bench_serving(fct, torch, duration, rate=200.0, slots=4):
     """The serving workload: requests drawn (seeded) from a pool of 64 jobs
     of four kinds (D2 |n|_1<=16; D6 |n|_1<=12 exp-cos; a batched-workload
@@ -355,9 +397,11 @@ def main():
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-precision", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=3)
-    ap.add_argument("--only", choices=["batched", "serving", "precision"],
+    ap.add_argument("--only", choices=["batched", "serving", "precision", "sparse"],
                     help="run one sub-workload alone and print its JSON (for profiling)")
     ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--skip-sparse", action="store_true",
+                    help="skip the D=100 sparse-support (f3) runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy five times (counter calibration)")
     args = ap.parse_args()
@@ -387,6 +431,9 @@ def main():
     if args.only == "precision":
         print(json.dumps({"precision_sweep": bench_precision(fct, torch, args.precision_steps)}),
               flush=True)
+        return
+    if args.only == "sparse":
+        print(json.dumps({"sparse_recovery": bench_sparse(fct, torch)}), flush=True)
         return
     if args.only == "serving":
         print(json.dumps({"serving": bench_serving(fct, torch, args.serving_seconds)}), flush=True)
@@ -468,6 +515,8 @@ def main():
                        "eval_terms_per_s": 5000 * prob.n / t_eval}
     plan.close()
     out["grid_selection"] = bench_grid_selection(fct, torch, prob)
+    if not args.skip_sparse:
+        out["sparse_recovery"] = bench_sparse(fct, torch)
     if not args.skip_batched:
         out["batched"] = bench_batched(fct, torch, args.batched_steps,
                                        args.batched_modes.split(","))
