@@ -1113,6 +1113,8 @@ static fct_status ensure_graph(fct_ws* ws, const CglsArgs& a, int chunk) {
 // predicts how many iterations remain and shortens the next chunk
 // accordingly, so few (early-exiting) launches run after the last problem
 // has converged.  Returns the number of iterations enqueued.
+constexpr int kWarmChunks = 3;   // short chunks at the start of a CGLS run
+
 static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, int k0, int maxit,
                             int chunk, bool use_graph, int32_t fused, hipStream_t s,
                             int* queued_out) {
@@ -1128,10 +1130,19 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
   std::vector<int> kprev((size_t)P, -1), klast((size_t)P, -1);
   std::vector<double> gprev((size_t)P, 0.0), glast((size_t)P, 0.0);
   int target = maxit;
+  // The first chunks are short: iterations queued past a problem's stop are
+  // wasted for a single problem (its kernels issue their loads before they
+  // read the stop flag), and the remaining-iteration estimate needs two
+  // finished chunks, so a run of a few tens of iterations would otherwise
+  // queue two full chunks before the first feedback.
+  const int warm = std::max(4, chunk / 4);
+  int nchunks = 0;
   while (true) {
     while (inflight < 2 && queued < maxit && queued < target) {
-      int c = std::min(chunk, std::min(maxit, target) - queued);
+      const int want = nchunks < kWarmChunks ? std::min(warm, chunk) : chunk;
+      int c = std::min(want, std::min(maxit, target) - queued);
       if (c < 1) c = 1;
+      ++nchunks;
       if (fused > 0) {
         FCT_HIP(launch_cgls_fused(a, c, fused, ws->d_bar, ws->d_bar + 2, s));
         FCT_HIP(launch_cgls_advance(a.state, c, s));
