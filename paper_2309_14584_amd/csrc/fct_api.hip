@@ -1139,8 +1139,14 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
   int nchunks = 0;
   while (true) {
     while (inflight < 2 && queued < maxit && queued < target) {
-      const int want = nchunks < kWarmChunks ? std::min(warm, chunk) : chunk;
-      int c = std::min(want, std::min(maxit, target) - queued);
+      // near the predicted end, queue half of what remains: the estimate
+      // tends to run long (CG converges faster near the end), so the last
+      // chunks shrink and a stop is seen before many iterations are wasted
+      const int remaining = std::min(maxit, target) - queued;
+      int want = nchunks < kWarmChunks ? std::min(warm, chunk) : chunk;
+      if (target < maxit && remaining <= 2 * chunk)
+        want = std::min(want, std::max(warm / 2, (remaining + 1) / 2));
+      int c = std::min(want, remaining);
       if (c < 1) c = 1;
       ++nchunks;
       if (fused > 0) {
