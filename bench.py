@@ -498,6 +498,26 @@ def main():
     torch.cuda.synchronize()
     out["roofline"] = roofline_rows(plan, tinfo.rows_kernel_us)
     out["roofline"]["cols_kernel_us"] = tinfo.cols_kernel_us
+    # the solve alone, CGLS (two kernels per iteration) beside the
+    # one-reduction CG on the normal equations (one kernel per iteration)
+    variants = {}
+    for name, kw in (("cgls", {}), ("one_reduction", {"one_reduction": True})):
+        for _ in range(3):
+            plan.solve(b, out=c, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            vinfo = plan.solve(b, out=c, **kw)[1]
+        torch.cuda.synchronize()
+        solve_ms = 1e3 * (time.perf_counter() - t0) / 20
+        err_v = float(np.max(np.abs(c.cpu().numpy() - c_gold)) / np.max(np.abs(c_gold)))
+        vt = plan.solve(b, out=c, timing=True, **kw)[1]
+        variants[name] = {"solve_ms": solve_ms,
+                          "iterations": vinfo.iterations,
+                          "kernel_us_per_iteration": vt.rows_kernel_us + vt.cols_kernel_us,
+                          "max_rel_err": err_v}
+    out["solve_variants"] = variants
+    plan.solve(b, out=c)
     # accuracy of the recovered expansion (the paper's sup-norm error at
     # random points), evaluated on the GPU (fct_eval); f itself on the host
     X = np.random.default_rng(5).uniform(-1, 1, size=(5000, prob.D))

@@ -162,7 +162,17 @@ typedef struct fct_solve_opts {
                            on MI355X about 6x slower, since every barrier's
                            agent-scope fences write back and invalidate L2);
                            0 (default): two kernels per iteration */
-  int32_t reserved2;
+  int32_t one_reduction; /* 1: FP64 solve of a single-problem plan as conjugate
+                           gradients on A^T A c = A^T b with one reduction per
+                           iteration (Chronopoulos-Gear recurrences; the CGLS
+                           iterates in exact arithmetic, rounded differently):
+                           one kernel per iteration that forms A^T A r by
+                           gathering each row's members, instead of the row
+                           and column kernels; for problems whose kernels are
+                           bound by latency.  Timing mode then reports that
+                           kernel in rows_kernel_us (cols_kernel_us 0).
+                           FCT_EINVAL with a batch, FP32 modes or
+                           single_kernel.  0 (default): CGLS */
 } fct_solve_opts;
 
 typedef struct fct_solve_info {

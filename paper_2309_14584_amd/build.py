@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfct.so")
 
 SOURCES = ["fct_api.hip", "plan_kernels.hip", "dct_kernels.hip", "sample_kernels.hip",
-           "cgls_kernels.hip", "eval_kernels.hip", "cond_kernels.hip"]
+           "cgls_kernels.hip", "eval_kernels.hip", "cond_kernels.hip", "cg1_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -749,6 +749,10 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   FCT_HIP(hipHostMalloc((void**)&w->h_gtrue, sizeof(double) * 2 * P, hipHostMallocDefault));
   FCT_HIP(dalloc(&w->d_part_q, 4 * p->nrblk, nullptr));   // one per wave of a row block
   FCT_HIP(dalloc(&w->d_part_s, p->ncblk, nullptr));
+  if (P == 1) {
+    FCT_HIP(dalloc(&w->d_cg, 2 * p->n, nullptr));
+    FCT_HIP(dalloc(&w->d_cg_part, 4 * ceil_div(p->n, kCg1Block), nullptr));
+  }
   FCT_HIP(dalloc(&w->d_ring, 8 * P, nullptr));
   FCT_HIP(dalloc(&w->d_gamma0, P, nullptr));
   FCT_HIP(dalloc(&w->d_done, P, nullptr));
@@ -776,6 +780,7 @@ void fct_ws_destroy(fct_ws* w) {
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
   dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
   dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_ring); dfree(w->d_gamma0);
+  dfree(w->d_cg); dfree(w->d_cg_part); dfree(w->d_nb8); dfree(w->d_nb_off); dfree(w->d_nb_ovf);
   dfree(w->d_done); dfree(w->d_flags); dfree(w->d_done_tmp); dfree(w->d_state);
   dfree(w->d_state_tmp); dfree(w->d_bar); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
   dfree(w->d_outer);
@@ -1079,6 +1084,51 @@ fct_status fct_apply_AT(const fct_plan* p, const double* d_r, double* d_s, hipSt
   return FCT_OK;
 }
 
+// Neighbour lists of the one-reduction solve (built on its first use with
+// this workspace): counts on the device, overflow offsets on the host.
+static fct_status ensure_neighbours(const fct_plan* p, fct_ws* ws, hipStream_t s) {
+  if (ws->d_nb8) return FCT_OK;
+  dfree(ws->d_nb_off);
+  dfree(ws->d_nb_ovf);
+  const int64_t n = p->n;
+  FCT_HIP(dalloc(&ws->d_nb_off, n + 1, nullptr));
+  FCT_HIP(launch_cg1_count(p->d_cblk, p->ncblk, p->d_rowmap, p->d_seg_off, ws->d_nb_off, s));
+  std::vector<int32_t> h((size_t)n + 1, 0);
+  FCT_HIP(hipMemcpyAsync(h.data(), ws->d_nb_off, sizeof(int32_t) * (size_t)n,
+                         hipMemcpyDeviceToHost, s));
+  FCT_HIP(hipStreamSynchronize(s));
+  int64_t tot = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    const int32_t c = h[(size_t)j];
+    h[(size_t)j] = (int32_t)tot;
+    tot += c > kNbSlots ? c - kNbSlots : 0;
+    if (tot > INT32_MAX) {
+      set_error("one_reduction: neighbour lists exceed 2^31 entries");
+      return FCT_EINVAL;
+    }
+  }
+  h[(size_t)n] = (int32_t)tot;
+  FCT_HIP(hipMemcpyAsync(ws->d_nb_off, h.data(), sizeof(int32_t) * (size_t)(n + 1),
+                         hipMemcpyHostToDevice, s));
+  FCT_HIP(dalloc(&ws->d_nb_ovf, tot, nullptr));
+  int4* nb8 = nullptr;
+  FCT_HIP(dalloc(&nb8, 2 * n, nullptr));
+  hipError_t e = launch_cg1_fill(p->d_cblk, p->ncblk, p->d_rowmap, p->d_seg_off, p->d_perm,
+                                 ws->d_nb_off, (int32_t)n, nb8, ws->d_nb_ovf, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    dfree(nb8);
+    FCT_HIP(e);
+  }
+  ws->d_nb8 = nb8;
+  return FCT_OK;
+}
+
+// One iteration: two kernels (CGLS), or one (the one-reduction variant).
+static hipError_t launch_iteration(const CglsArgs& a, int rel, hipStream_t s) {
+  return a.cg1 ? launch_cg1_iter(a, rel, s) : launch_cgls_iter(a, rel, s);
+}
+
 // Graph of `chunk` CGLS iterations for the given arguments (cached per
 // precision in the workspace; rebuilt when the chunk or any argument
 // changes -- the output, the tolerance, or the plan's block tables, which
@@ -1093,7 +1143,7 @@ static fct_status ensure_graph(fct_ws* ws, const CglsArgs& a, int chunk) {
   hipGraph_t gr = nullptr;
   FCT_HIP(hipStreamBeginCapture(ws->graph_stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int rel = 0; rel < chunk && e == hipSuccess; ++rel) e = launch_cgls_iter(a, rel, ws->graph_stream);
+  for (int rel = 0; rel < chunk && e == hipSuccess; ++rel) e = launch_iteration(a, rel, ws->graph_stream);
   if (e == hipSuccess) e = launch_cgls_advance(a.state, chunk, ws->graph_stream);
   hipError_t e2 = hipStreamEndCapture(ws->graph_stream, &gr);
   if (e != hipSuccess) { if (gr) (void)hipGraphDestroy(gr); return hip_fail(e, "graph capture", __FILE__, __LINE__); }
@@ -1155,7 +1205,7 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
       } else if (use_graph && c == chunk) {
         FCT_HIP(hipGraphLaunch(ws->graph_exec[g], s));
       } else {
-        for (int rel = 0; rel < c; ++rel) FCT_HIP(launch_cgls_iter(a, rel, s));
+        for (int rel = 0; rel < c; ++rel) FCT_HIP(launch_iteration(a, rel, s));
         FCT_HIP(launch_cgls_advance(a.state, c, s));
       }
       queued += c;
@@ -1227,16 +1277,18 @@ static fct_status time_kernels(fct_ws* ws, const CglsArgs& a, int k, int P, hipS
   struct EG { hipEvent_t* e; ~EG() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } eg{ev};
   for (auto& e : ev) FCT_HIP(hipEventCreate(&e));
   FCT_HIP(hipEventRecord(ev[0], s));
-  for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_rows(t, 0, s));
+  for (int i = 0; i < kReps; ++i)
+    FCT_HIP(t.cg1 ? launch_cg1_iter(t, 0, s) : launch_cgls_rows(t, 0, s));
   FCT_HIP(hipEventRecord(ev[1], s));
-  for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_cols(t, 0, s));
+  if (!t.cg1)
+    for (int i = 0; i < kReps; ++i) FCT_HIP(launch_cgls_cols(t, 0, s));
   FCT_HIP(hipEventRecord(ev[2], s));
   FCT_HIP(hipEventSynchronize(ev[2]));
   float m1 = 0.f, m2 = 0.f;
   FCT_HIP(hipEventElapsedTime(&m1, ev[0], ev[1]));
   FCT_HIP(hipEventElapsedTime(&m2, ev[1], ev[2]));
   *rows_us = 1e3 * m1 / kReps;
-  *cols_us = 1e3 * m2 / kReps;
+  *cols_us = t.cg1 ? 0.0 : 1e3 * m2 / kReps;
   return FCT_OK;
 }
 
@@ -1260,6 +1312,11 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   if (o.tol <= 0.0) o.tol = o.mode == FCT_SOLVE_F32 ? 2e-7 : 1e-14;
   if (o.check_every > 4096) o.check_every = 4096;
   if (o.maxit > (1 << 30)) { set_error("maxit too large"); return FCT_EINVAL; }
+  if (o.one_reduction != 0 &&
+      (mixed || p->nprob != 1 || o.single_kernel > 0 || !ws->d_cg)) {
+    set_error("one_reduction needs an FP64 solve of a single-problem plan (two-kernel form)");
+    return FCT_EINVAL;
+  }
   if (o.max_refine <= 0) o.max_refine = 12;
   if (o.inner_tol <= 0.0) o.inner_tol = 1e-5;
   const int P = p->nprob;
@@ -1277,6 +1334,20 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   a.state = ws->d_state;
   a.r64 = ws->d_r64; a.part_true = ws->d_part_true; a.gtrue0 = ws->d_gtrue;
   a.gtrue = ws->d_gtrue + P; a.outer_done = ws->d_outer;
+  if (o.one_reduction != 0) {
+    st = ensure_neighbours(p, ws, s);
+    if (st != FCT_OK) return st;
+    a.cg1 = 1;
+    a.nb8 = ws->d_nb8;
+    a.nb_off = ws->d_nb_off;
+    a.nb_ovf = ws->d_nb_ovf;
+    a.cg1_n = (int32_t)p->n;
+    a.cg1_K = p->K;
+    a.cg1_nblk = (int32_t)ceil_div(p->n, kCg1Block);
+    a.cg[0] = ws->d_cg;
+    a.cg[1] = ws->d_cg + p->n;
+    a.cg_part = ws->d_cg_part;
+  }
   const int chunk = o.check_every;
   // on request, one problem whose blocks each fit a resident workgroup: one
   // kernel per chunk of iterations (grid barriers between the phases)
@@ -1296,6 +1367,7 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   if (!mixed) {
     a.tol2 = o.tol * o.tol;
     FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
+    if (a.cg1) FCT_HIP(launch_cg1_init(a, s));
     st = cgls_loop(p, ws, a, 0, o.maxit, chunk, o.use_graph != 0, fused, s, &last_queued);
     if (st != FCT_OK) return st;
     total_queued = last_queued;
@@ -1303,7 +1375,8 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     FCT_HIP(hipStreamSynchronize(s));
     bool any_running = false;
     for (int q = 0; q < P; ++q) any_running |= fd[q] == 0;
-    if (any_running) FCT_HIP(launch_cgls_gamma(a, last_queued, s));
+    if (any_running)
+      FCT_HIP(a.cg1 ? launch_cg1_gamma(a, last_queued, s) : launch_cgls_gamma(a, last_queued, s));
     FCT_HIP(hipMemcpyAsync(fr, a.ring, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, s));
     FCT_HIP(hipMemcpyAsync(fg0, a.gamma0, sizeof(double) * P, hipMemcpyDeviceToHost, s));
     FCT_HIP(hipMemcpyAsync(ws->h_flags, a.flags, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
@@ -1412,7 +1485,9 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   agg.iterations = max_iter;
   agg.converged = agg.problems_converged == P ? 1 : 0;
   if (o.timing && last_queued > 0) {
-    st = time_kernels(ws, a, std::max(0, last_queued - 1), P, s, &agg.rows_kernel_us,
+    // the one-reduction kernel is timed as its first iteration (no ring
+    // entries of earlier ones needed)
+    st = time_kernels(ws, a, a.cg1 ? 0 : std::max(0, last_queued - 1), P, s, &agg.rows_kernel_us,
                       &agg.cols_kernel_us);
     if (st != FCT_OK) return st;
   }

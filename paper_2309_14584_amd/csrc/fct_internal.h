@@ -240,8 +240,37 @@ struct CglsArgs {
   const RowBlock* rblk32;
   int64_t nrblk32;
   int32_t lds_bytes;  // dynamic LDS of the unit kernel
+  // one-reduction CG (one problem, FP64): (r, w, s, p) per column in two
+  // buffers by iteration parity, [2 parities][gamma, delta][cg1_nblk] partials,
+  // and each column's neighbour list (the other members of its K rows, in
+  // grid order, repeated when two columns share several rows): the first
+  // eight in nb8 ([2][n] int4, -1 padded), the rest in
+  // nb_ovf[nb_off[j] .. nb_off[j+1])
+  int32_t cg1;
+  double4* cg[2];
+  double* cg_part;
+  const int4* nb8;
+  const int32_t* nb_off;
+  const int32_t* nb_ovf;
+  int32_t cg1_n;      // columns
+  int32_t cg1_K;      // grids
+  int32_t cg1_nblk;   // one-wave workgroups (kCg1Block columns each)
 };
+constexpr int kCg1Block = 64;
+constexpr int kNbSlots = 8;
 hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipStream_t s);
+// one-reduction CG: init after launch_cgls_init, one kernel per iteration
+hipError_t launch_cg1_init(const CglsArgs& a, hipStream_t s);
+// neighbour lists of a single-problem plan: counts (other members over the
+// K rows of each column) into cnt[n], then the lists from the overflow
+// offsets off[n+1] (entries beyond the eighth)
+hipError_t launch_cg1_count(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
+                            const int32_t* seg_off, int32_t* cnt, hipStream_t s);
+hipError_t launch_cg1_fill(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
+                           const int32_t* seg_off, const int32_t* perm, const int32_t* off,
+                           int32_t n, int4* nb8, int32_t* ovf, hipStream_t s);
+hipError_t launch_cg1_iter(const CglsArgs& a, int rel, hipStream_t s);
+hipError_t launch_cg1_gamma(const CglsArgs& a, int k, hipStream_t s);
 hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s);
 hipError_t launch_cgls_rows(const CglsArgs& a, int rel, hipStream_t s);
 hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s);
@@ -349,6 +378,11 @@ struct fct_ws {
   double* h_gprev = nullptr;       // pinned [nprob]
   double* d_part_q = nullptr;      // [4 nrblk] per-wave partials of ||q||^2
   double* d_part_s = nullptr;      // [ncblk]
+  double4* d_cg = nullptr;         // [2][n] one-reduction CG state (single problem)
+  double* d_cg_part = nullptr;     // [2][2][ceil(n/kCg1Block)] its partials
+  int4* d_nb8 = nullptr;           // [2][n] neighbour lists (built on first use)
+  int32_t* d_nb_off = nullptr;     // [n+1]
+  int32_t* d_nb_ovf = nullptr;     // [max(1, overflow entries)]
   double* d_ring = nullptr;        // [nprob][8]
   double* d_gamma0 = nullptr;      // [nprob]
   int32_t* d_done = nullptr;       // [nprob]

@@ -49,7 +49,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("mode", _i32), ("maxit", _i32), ("check_every", _i32),
                 ("warm_start", _i32), ("use_graph", _i32), ("timing", _i32),
                 ("tol", _dbl), ("max_refine", _i32), ("restart_rounds", _i32),
-                ("inner_tol", _dbl), ("single_kernel", _i32), ("reserved2", _i32)]
+                ("inner_tol", _dbl), ("single_kernel", _i32), ("one_reduction", _i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -426,13 +426,13 @@ class Plan:
     def solve(self, b, out=None, tol=0.0, maxit=0, check_every=0, warm_start=False,
               use_graph=True, mode=SOLVE_F64, raise_on_noconv=True, timing=False,
               max_refine=0, inner_tol=0.0, restart_rounds=False, single_kernel=False,
-              stream=None, ws=None):
+              one_reduction=False, stream=None, ws=None):
         torch = _torch()
         out = self._empty(self.n) if out is None else out
         opts = SolveOpts(mode, int(maxit), int(check_every), 1 if warm_start else 0,
                          1 if use_graph else 0, 1 if timing else 0, float(tol),
                          int(max_refine), 1 if restart_rounds else 0, float(inner_tol),
-                         1 if single_kernel else 0, 0)
+                         1 if single_kernel else 0, 1 if one_reduction else 0)
         info = SolveInfo()
         st = _solve(self._h, _ptr(b, torch.float64, self.M, "b"),
                     _ptr(out, torch.float64, self.n, "out"), ctypes.byref(opts),
