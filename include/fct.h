@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FCT_ABI_VERSION 2
+#define FCT_ABI_VERSION 3
 #define FCT_MAX_DIM 128      /* largest D accepted */
 #define FCT_MAX_DEGREE 63    /* largest Lobatto degree N_i (64 nodes) */
 
@@ -117,6 +117,21 @@ typedef enum fct_solve_mode {
 
 /* Plan creation flags. */
 #define FCT_PLAN_ALLOW_RANK_DEFICIENT 1u /* skip the per-dimension rank pre-check */
+/* The paper's literal operator (Sec. 2 "Problem setup", Sec. 3.1, Lemma 3.1):
+ * Chebyshev-Gauss grids x_k = cos(pi (k + 1/2) / (N + 1)), k = 0..N, and the
+ * DCT-II a_m = (g_m 2 / (N + 1)) sum_k v_k cos(pi m (2k + 1) / (2 (N + 1))),
+ * g_0 = 1/2 else 1 (the quadrature of eq. quad_1D with rows m >= 1 doubled,
+ * so that samples of T_m, m <= N, map to e_m).  T_a then equals s T_m on
+ * the nodes with r = a mod 2(N+1), m = min(r, 2(N+1) - r) and the sign
+ * s = (-1)^(a div 2(N+1)) for r < N + 1, its negation for r > N + 1; at
+ * r = N + 1 (T_{N+1}) it vanishes.  A's entries are the products of the 1-D
+ * signs over the axes, in {-1, 0, 1}; a zero entry stays in the structure
+ * (bin with m_i = N_i) with weight 0.  A Gauss plan: single problem (not
+ * batched), FP64 solves only, solved by the one-reduction CG (see
+ * fct_solve_opts.one_reduction, implied); sampling, transforms, apply,
+ * condition estimate and evaluation as for Lobatto plans.  N_i = 0 is the
+ * single node x = 0. */
+#define FCT_PLAN_GAUSS 2u
 
 typedef struct fct_plan fct_plan;
 typedef struct fct_ws fct_ws;
@@ -212,6 +227,9 @@ int32_t fct_abi_version(void);
  * when some dimension i has two degrees a != a' <= max_j n_ji with
  * fold(a, N_i^(l)) = fold(a', N_i^(l)) on every grid (two coefficients that
  * differ only in entry i would then be indistinguishable).
+ * With FCT_PLAN_GAUSS the pre-check asks, per dimension, that every degree's
+ * signed 1-D rows over the K grids be nonzero (T_a does not vanish on every
+ * grid) and that no two degrees have the same rows up to sign.
  * Limits (else FCT_EINVAL): 1 <= D <= FCT_MAX_DIM, n_support >= 1,
  * 1 <= K < 2^19, K * n_support < 2^31, each grid's point count < 2^44,
  * 0 <= N_i <= FCT_MAX_DEGREE, duplicate support rows rejected.
@@ -232,8 +250,13 @@ fct_status fct_plan_grid(const fct_plan* plan, int32_t grid, int64_t* points,
 fct_status fct_plan_export(const fct_plan* plan, int64_t* d_alias, int32_t* d_perm,
                            int32_t* d_seg_off, int64_t* d_bin_id, int32_t* d_rowmap,
                            hipStream_t stream);
+/* Entry weights of A (Gauss plans: the sign in {-1, 0, 1} of support row j on
+ * grid l; Lobatto plans: all 1) into d_w int8 [K*n], layout of alias.
+ * Single-problem plans.  Asynchronous on `stream`. */
+fct_status fct_plan_weights(const fct_plan* plan, int8_t* d_w, hipStream_t stream);
 /* Node coordinates of grid `grid` along dimension `dim` as used by the
- * sampler: host_out[k] = cos(pi k / N), k = 0..N (synchronous). */
+ * sampler: host_out[k] = cos(pi k / N), k = 0..N, or for a Gauss plan
+ * cos(pi (k + 1/2) / (N + 1)) (synchronous). */
 fct_status fct_grid_nodes(const fct_plan* plan, int32_t grid, int32_t dim,
                           double* host_out);
 
@@ -344,6 +367,7 @@ fct_status fct_eval(const fct_plan* plan, const double* d_c, int64_t m, const do
  *               (double [n] -> double [M]); summed in perm order.
  * fct_apply_AT: d_s[j] = sum_l d_r[rowmap[l][j]] (double [M] -> double [n]),
  *               summed in grid order.  No atomics: results are reproducible.
+ * For a Gauss plan every term carries its entry weight (fct_plan_weights).
  */
 fct_status fct_apply_A(const fct_plan* plan, const double* d_c, double* d_q,
                        hipStream_t stream);

@@ -17,7 +17,10 @@
 // a neighbour counted once per shared row).  Each neighbour's new r =
 // r - alpha (w + beta s) is linear in its stored values, so the kernel
 // gathers the neighbours' (r, w, s) and sums them before the scalars are
-// known: one level of dependent loads past the list.  The state alternates
+// known: one level of dependent loads past the list.  On a Gauss plan A
+// has entries in {-1, 0, 1}: a neighbour carries the sign of the product of
+// the two entries, and the diagonal is the number of grids where the
+// column's entry is nonzero (kept per column).  The state alternates
 // between two buffers by iteration parity (workgroups gather the old state
 // while others write the new one); so do the partials.
 #include "fct_internal.h"
@@ -55,9 +58,11 @@ __device__ __forceinline__ double share(const double* __restrict__ part, int32_t
   return r;
 }
 
-// Calls f(m) for every entry m of column j's neighbour list: the eight
+// Calls f(m, sign) for every entry of column j's neighbour list: the eight
 // slots, then the overflow four at a time (indices loaded before the
-// gathers), so that a long list costs few dependent loads.
+// gathers), so that a long list costs few dependent loads.  An entry e >= 0
+// is neighbour e with sign +1, e <= -2 neighbour -e - 2 with sign -1 (Gauss
+// plans), -1 an empty slot.
 template <typename F>
 __device__ __forceinline__ void for_neighbours(const CglsArgs& a, int32_t j, F&& f) {
   const int4 e0 = a.nb8[j];
@@ -66,32 +71,54 @@ __device__ __forceinline__ void for_neighbours(const CglsArgs& a, int32_t j, F&&
   const int32_t m[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
 #pragma unroll
   for (int u = 0; u < 8; ++u)
-    if (m[u] >= 0) f(m[u]);
+    if (m[u] != -1) f(m[u] >= 0 ? m[u] : -m[u] - 2, m[u] >= 0 ? 1.0 : -1.0);
   for (int32_t t = t0; t < t1; t += 4) {
     int32_t i[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) i[u] = t + u < t1 ? a.nb_ovf[t + u] : -1;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (i[u] >= 0) f(i[u]);
+      if (i[u] != -1) f(i[u] >= 0 ? i[u] : -i[u] - 2, i[u] >= 0 ? 1.0 : -1.0);
   }
 }
 
-// Neighbour counts: the other members of the column's K rows.
+// Weight of entry t of the [K][n] maps (1 without a weight table).
+__device__ __forceinline__ int wt(const int8_t* __restrict__ w, int64_t t) {
+  return w ? (int)w[t] : 1;
+}
+
+// Neighbour counts: the other members of the column's K rows with nonzero
+// weight (rows where the column itself has weight 0 add none), and the
+// diagonal of A^T A: the number of grids where the column's weight is
+// nonzero.  perm entry t belongs to grid t / n.
 __global__ __launch_bounds__(kBlock) void cg1_count_kernel(const ColBlock* __restrict__ cblk,
                                                            const int32_t* __restrict__ rowmap,
                                                            const int32_t* __restrict__ seg_off,
-                                                           int32_t* __restrict__ cnt) {
+                                                           const int32_t* __restrict__ perm,
+                                                           const int8_t* __restrict__ w,
+                                                           int32_t* __restrict__ cnt,
+                                                           int32_t* __restrict__ diag) {
   const ColBlock bd = cblk[blockIdx.x];
   const int32_t j = bd.col0 + threadIdx.x;
   if (j >= bd.col_end) return;
   const int32_t jl = j - bd.col_off;
-  int32_t c = 0;
+  int32_t c = 0, dg = 0;
   for (int l = 0; l < bd.K; ++l) {
-    const int32_t row = rowmap[bd.rmap_off + l * bd.n + jl];
-    c += seg_off[row + 1] - seg_off[row] - 1;
+    const int64_t tj = bd.rmap_off + (int64_t)l * bd.n + jl;
+    if (wt(w, tj) == 0) continue;
+    ++dg;
+    const int32_t row = rowmap[tj];
+    if (!w) {
+      c += seg_off[row + 1] - seg_off[row] - 1;
+      continue;
+    }
+    for (int32_t t = seg_off[row]; t < seg_off[row + 1]; ++t) {
+      const int32_t m = perm[t];
+      if (m != j && w[(int64_t)l * bd.n + m] != 0) ++c;
+    }
   }
   cnt[j] = c;
+  diag[j] = dg;
 }
 
 // Neighbour lists in grid order, then run order within a row: slot u of
@@ -100,6 +127,7 @@ __global__ __launch_bounds__(kBlock) void cg1_fill_kernel(const ColBlock* __rest
                                                           const int32_t* __restrict__ rowmap,
                                                           const int32_t* __restrict__ seg_off,
                                                           const int32_t* __restrict__ perm,
+                                                          const int8_t* __restrict__ w,
                                                           const int32_t* __restrict__ off,
                                                           int32_t n, int32_t* __restrict__ nb8,
                                                           int32_t* __restrict__ ovf) {
@@ -114,16 +142,88 @@ __global__ __launch_bounds__(kBlock) void cg1_fill_kernel(const ColBlock* __rest
   int32_t idx = 0;
   const int32_t o = off[j], o_end = off[j + 1];
   for (int l = 0; l < bd.K; ++l) {
-    const int32_t row = rowmap[bd.rmap_off + l * bd.n + jl];
+    const int64_t tj = bd.rmap_off + (int64_t)l * bd.n + jl;
+    const int wj = wt(w, tj);
+    if (wj == 0) continue;
+    const int32_t row = rowmap[tj];
     const int32_t t1 = seg_off[row + 1];
     for (int32_t t = seg_off[row]; t < t1; ++t) {
       const int32_t m = perm[t];
       if (m == j) continue;
-      if (idx < kNbSlots) slot(idx) = m;
-      else if (o + idx - kNbSlots < o_end) ovf[o + idx - kNbSlots] = m;
+      const int wm = wt(w, (int64_t)l * bd.n + m);
+      if (wm == 0) continue;
+      const int32_t e = wj * wm > 0 ? m : -m - 2;
+      if (idx < kNbSlots) slot(idx) = e;
+      else if (o + idx - kNbSlots < o_end) ovf[o + idx - kNbSlots] = e;
       ++idx;
     }
   }
+}
+
+// q = A c with entry weights (Gauss plans): row r's run in perm, entry t of
+// grid t / n, summed in run order.
+__global__ __launch_bounds__(kBlock) void apply_A_signed_kernel(
+    const int32_t* __restrict__ seg_off, const int32_t* __restrict__ perm,
+    const int8_t* __restrict__ w, int64_t M, int64_t n, const double* __restrict__ c,
+    double* __restrict__ q) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= M) return;
+  double acc = 0.0;
+  for (int32_t t = seg_off[r]; t < seg_off[r + 1]; ++t) {
+    const int32_t j = perm[t];
+    acc = fma((double)w[(t / n) * n + j], c[j], acc);
+  }
+  q[r] = acc;
+}
+
+// s = A^T r with entry weights: sum over the grids in order.
+__global__ __launch_bounds__(kBlock) void apply_AT_signed_kernel(
+    const int32_t* __restrict__ rowmap, const int8_t* __restrict__ w, int32_t K, int64_t n,
+    const double* __restrict__ r, double* __restrict__ s) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int l = 0; l < K; ++l) {
+    const int64_t t = (int64_t)l * n + j;
+    acc = fma((double)w[t], r[rowmap[t]], acc);
+  }
+  s[j] = acc;
+}
+
+// Gauss plans, start of a solve: r_0 = b - A c_0 into r64 (c_0 = 0 unless
+// warm) and the iteration state reset.
+__global__ __launch_bounds__(kBlock) void gauss_init_rows_kernel(CglsArgs a,
+                                                                 const int8_t* __restrict__ w,
+                                                                 const double* __restrict__ b,
+                                                                 int64_t M, int warm) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) { a.state[0] = 0; a.state[1] = 0; a.done[0] = 0; a.flags[0] = 0; }
+  if (r >= M) return;
+  double acc = 0.0;
+  if (warm) {
+    const int64_t n = a.cg1_n;
+    for (int32_t t = a.seg_off[r]; t < a.seg_off[r + 1]; ++t) {
+      const int32_t j = a.perm[t];
+      acc = fma((double)w[(t / n) * n + j], a.c[j], acc);
+    }
+  }
+  a.r64[r] = b[r] - acc;
+}
+
+// s_0 = A^T r_0 into ps.y (ps.x = 0), c = 0 unless warm.
+__global__ __launch_bounds__(kBlock) void gauss_init_cols_kernel(CglsArgs a,
+                                                                 const int8_t* __restrict__ w,
+                                                                 int warm) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = a.cg1_n;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int l = 0; l < a.cg1_K; ++l) {
+    const int64_t t = (int64_t)l * n + j;
+    acc = fma((double)w[t], a.r64[a.rowmap[t]], acc);
+  }
+  static_cast<double2*>(a.ps)[j] = make_double2(0.0, acc);
+  if (!warm) a.c[j] = 0.0;
 }
 
 // w = A^T A s_0 and gamma_0, delta_0 from the normal residual s_0 that the
@@ -135,8 +235,8 @@ __global__ __launch_bounds__(kCg1Block) void cg1_init_kernel(CglsArgs a) {
   double r = 0.0, w = 0.0;
   if (j < a.cg1_n) {
     r = ps[j].y;
-    for_neighbours(a, j, [&](int32_t m) { w += ps[m].y; });
-    w = fma((double)a.cg1_K, r, w);
+    for_neighbours(a, j, [&](int32_t m, double sg) { w = fma(sg, ps[m].y, w); });
+    w = fma((double)a.nb_diag[j], r, w);
     a.cg[0][j] = make_double4(r, w, 0.0, 0.0);
   }
   const double2 gd = wave_sum2(r * r, w * r);
@@ -166,10 +266,12 @@ __global__ __launch_bounds__(kCg1Block) void cg1_kernel(CglsArgs a, int rel) {
   const double gp = share(pin, nb);
   const double dp = share(pin + nb, nb);
   double R = 0.0, W = 0.0, S = 0.0;
+  double dg = 0.0;
   if (active) {
-    for_neighbours(a, j, [&](int32_t m) {
+    dg = (double)a.nb_diag[j];
+    for_neighbours(a, j, [&](int32_t m, double sg) {
       const double4 v = cur[m];
-      R += v.x; W += v.y; S += v.z;
+      R = fma(sg, v.x, R); W = fma(sg, v.y, W); S = fma(sg, v.z, S);
     });
   }
 
@@ -203,8 +305,8 @@ __global__ __launch_bounds__(kCg1Block) void cg1_kernel(CglsArgs a, int rel) {
     const double sv = fma(beta, own.z, own.y);       // s = w + beta s
     a.c[j] = fma(alpha, pv, c_old);
     rn = fma(-alpha, sv, own.x);                     // r - alpha s
-    // K rn plus the neighbours' new r
-    wn = fma((double)a.cg1_K, rn, R - alpha * fma(beta, S, W));
+    // (A^T A)_jj rn plus the neighbours' new r
+    wn = fma(dg, rn, R - alpha * fma(beta, S, W));
     nxt[j] = make_double4(rn, wn, sv, pv);
   }
   const double2 o = wave_sum2(rn * rn, wn * rn);
@@ -224,17 +326,46 @@ __global__ __launch_bounds__(kCg1Block) void cg1_gamma_kernel(CglsArgs a, int k)
 }  // namespace
 
 hipError_t launch_cg1_count(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
-                            const int32_t* seg_off, int32_t* cnt, hipStream_t s) {
+                            const int32_t* seg_off, const int32_t* perm, const int8_t* w,
+                            int32_t* cnt, int32_t* diag, hipStream_t s) {
   hipLaunchKernelGGL(cg1_count_kernel, dim3((unsigned)ncblk), dim3(kBlock), 0, s, cblk, rowmap,
-                     seg_off, cnt);
+                     seg_off, perm, w, cnt, diag);
   return hipGetLastError();
 }
 
 hipError_t launch_cg1_fill(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
-                           const int32_t* seg_off, const int32_t* perm, const int32_t* off,
-                           int32_t n, int4* nb8, int32_t* ovf, hipStream_t s) {
+                           const int32_t* seg_off, const int32_t* perm, const int8_t* w,
+                           const int32_t* off, int32_t n, int4* nb8, int32_t* ovf,
+                           hipStream_t s) {
   hipLaunchKernelGGL(cg1_fill_kernel, dim3((unsigned)ncblk), dim3(kBlock), 0, s, cblk, rowmap,
-                     seg_off, perm, off, n, reinterpret_cast<int32_t*>(nb8), ovf);
+                     seg_off, perm, w, off, n, reinterpret_cast<int32_t*>(nb8), ovf);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_A_signed(const int32_t* seg_off, const int32_t* perm, const int8_t* w,
+                                 int64_t M, int64_t n, const double* c, double* q,
+                                 hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(apply_A_signed_kernel, dim3((unsigned)ceil_div(M, kBlock)), dim3(kBlock), 0,
+                     s, seg_off, perm, w, M, n, c, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_AT_signed(const int32_t* rowmap, const int8_t* w, int32_t K, int64_t n,
+                                  const double* r, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(apply_AT_signed_kernel, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock),
+                     0, s, rowmap, w, K, n, r, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_init(const CglsArgs& a, const int8_t* w, const double* b, int64_t M,
+                             bool warm, hipStream_t s) {
+  hipLaunchKernelGGL(gauss_init_rows_kernel, dim3((unsigned)ceil_div(M > 0 ? M : 1, kBlock)),
+                     dim3(kBlock), 0, s, a, w, b, M, warm ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gauss_init_cols_kernel, dim3((unsigned)ceil_div(a.cg1_n, kBlock)),
+                     dim3(kBlock), 0, s, a, w, warm ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -48,6 +48,17 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// Gauss grid of N + 1 nodes: the aliased index and the sign (0: T_{N+1}
+// vanishes), as in the plan's alias kernel.
+int64_t fold_gauss_host(int64_t a, int32_t N, int* w) {
+  const int64_t g = (int64_t)N + 1, p = 2 * g, r = a % p;
+  const bool odd = ((a / p) & 1) != 0;
+  if (r == g) { *w = 0; return N; }
+  if (r < g) { *w = odd ? -1 : 1; return r; }
+  *w = odd ? 1 : -1;
+  return p - r;
+}
+
 int64_t fold_host(int64_t a, int32_t N) {
   if (N == 0) return 0;
   const int64_t p = 2 * (int64_t)N;
@@ -177,6 +188,7 @@ void destroy_plan(fct_plan* p) {
   if (!p) return;
   dfree(p->d_support); dfree(p->d_grids); dfree(p->d_strides); dfree(p->d_point_off);
   dfree(p->d_alias); dfree(p->d_perm); dfree(p->d_seg_off); dfree(p->d_bin_id);
+  dfree(p->d_wsign);
   dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_ell); dfree(p->d_nodes); dfree(p->d_cmat);
   dfree(p->d_emat); dfree(p->d_cmat32); dfree(p->d_rblk); dfree(p->d_cblk); dfree(p->d_prob);
   dfree(p->d_units); dfree(p->d_rblk32); dfree(p->d_ell16); dfree(p->d_sdesc);
@@ -348,7 +360,8 @@ fct_status build_tables(fct_plan* p, hipStream_t stream) {
   FCT_HIP(dalloc(&p->d_cmat, mat_offset(p->maxdeg + 1), bytes));
   FCT_HIP(dalloc(&p->d_cmat32, mat_offset(p->maxdeg + 1), bytes));
   FCT_HIP(dalloc(&p->d_emat, mat_offset(p->maxdeg + 1), bytes));
-  FCT_HIP(launch_tables(p->maxdeg, p->d_nodes, p->d_cmat, p->d_cmat32, p->d_emat, stream));
+  FCT_HIP(launch_tables(p->maxdeg, p->d_nodes, p->d_cmat, p->d_cmat32, p->d_emat, p->gauss,
+                        stream));
   return FCT_OK;
 }
 
@@ -389,7 +402,39 @@ fct_status validate_inputs(int32_t D, int64_t n, const int32_t* S, int32_t K, co
         return FCT_EINVAL;
       }
   }
-  if (!(flags & FCT_PLAN_ALLOW_RANK_DEFICIENT)) {
+  if (flags & ~(FCT_PLAN_ALLOW_RANK_DEFICIENT | FCT_PLAN_GAUSS)) {
+    set_error("unknown plan flags 0x%x", flags);
+    return FCT_EINVAL;
+  }
+  if ((flags & FCT_PLAN_GAUSS) && !(flags & FCT_PLAN_ALLOW_RANK_DEFICIENT)) {
+    // per dimension, the signed 1-D rows of every degree over the K grids
+    // must be nonzero and pairwise independent (not equal up to sign)
+    for (int i = 0; i < D; ++i) {
+      int32_t mx = 0;
+      for (int64_t j = 0; j < n; ++j) mx = std::max(mx, S[j * D + i]);
+      std::set<std::vector<int64_t>> seen;
+      for (int32_t a = 0; a <= mx; ++a) {
+        std::vector<int64_t> key((size_t)K);
+        int64_t first = 0;
+        for (int64_t l = 0; l < K; ++l) {
+          int w = 1;
+          const int64_t m = fold_gauss_host(a, G[l * D + i], &w);
+          key[(size_t)l] = w == 0 ? 0 : w * (m + 1);
+          if (first == 0) first = key[(size_t)l];
+        }
+        if (first == 0) {
+          set_error("rank pre-check: dimension %d, degree %d vanishes on every grid", i, a);
+          return FCT_ERANK;
+        }
+        if (first < 0) for (auto& v : key) v = -v;
+        if (!seen.insert(key).second) {
+          set_error("rank pre-check: dimension %d, degree %d aliases an earlier degree (up to "
+                    "sign) on every grid", i, a);
+          return FCT_ERANK;
+        }
+      }
+    }
+  } else if (!(flags & FCT_PLAN_ALLOW_RANK_DEFICIENT)) {
     // per dimension, the K folds must tell apart every degree that occurs
     for (int i = 0; i < D; ++i) {
       int32_t mx = 0;
@@ -424,6 +469,17 @@ struct DevGuard {
 };
 
 }  // namespace
+
+// A c and A^T r of a plan, with the entry weights of a Gauss plan.
+hipError_t plan_apply_A(const fct_plan* p, const double* c, double* q, hipStream_t s) {
+  if (p->gauss) return launch_apply_A_signed(p->d_seg_off, p->d_perm, p->d_wsign, p->M, p->n, c, q, s);
+  return launch_apply_A(p->d_seg_off, p->d_perm, p->M, c, q, s);
+}
+
+hipError_t plan_apply_AT(const fct_plan* p, const double* r, double* out, hipStream_t s) {
+  if (p->gauss) return launch_apply_AT_signed(p->d_rowmap, p->d_wsign, p->K, p->n, r, out, s);
+  return launch_apply_AT(p->d_cblk, p->ncblk, p->d_rowmap, r, out, s);
+}
 
 }  // namespace fct
 
@@ -470,6 +526,7 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   } guard{p};
 
   FCT_HIP(hipGetDevice(&p->device));
+  p->gauss = (flags & FCT_PLAN_GAUSS) ? 1 : 0;
   p->nprob = 1;
   p->D = D; p->K = K; p->n = n;
   p->grids.assign(grids, grids + (size_t)K * D);
@@ -501,6 +558,7 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   FCT_HIP(dalloc(&p->d_strides, (int64_t)K * D, bytes));
   FCT_HIP(dalloc(&p->d_point_off, (int64_t)K + 1, bytes));
   FCT_HIP(dalloc(&p->d_alias, L, bytes));
+  if (p->gauss) FCT_HIP(dalloc(&p->d_wsign, L, bytes));
   FCT_HIP(dalloc(&p->d_perm, L, bytes));
   FCT_HIP(dalloc(&p->d_seg_off, L + 1, bytes));
   FCT_HIP(dalloc(&p->d_bin_id, L, bytes));
@@ -521,7 +579,7 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
   st = build_tables(p, stream);
   if (st != FCT_OK) return st;
   FCT_HIP(launch_alias(p->d_support, p->d_grids, p->d_strides, D, n, K, p->d_alias, guard.k0,
-                       guard.v0, stream));
+                       guard.v0, p->d_wsign, stream));
   bool in_tmp = false;
   FCT_HIP(launch_sort(guard.k0, guard.v0, guard.k1, guard.v1, L, &in_tmp, stream));
   const uint64_t* ks = in_tmp ? guard.k1 : guard.k0;
@@ -574,6 +632,7 @@ fct_status fct_batch_create(int32_t count, const fct_plan* const* plans, hipStre
   for (int32_t q = 0; q < count; ++q) {
     const fct_plan* s = plans[q];
     if (!s || s->nprob != 1) { set_error("plan %d is NULL or already a batch", q); return FCT_EINVAL; }
+    if (s->gauss) { set_error("plan %d is a Gauss-grid plan (not batched)", q); return FCT_EINVAL; }
     if (s->device != dev) { set_error("plan %d lives on another device", q); return FCT_EINVAL; }
     Lsum += (int64_t)s->K * s->n;
     Msum += s->M;
@@ -713,6 +772,16 @@ fct_status fct_plan_export(const fct_plan* p, int64_t* d_alias, int32_t* d_perm,
   return FCT_OK;
 }
 
+fct_status fct_plan_weights(const fct_plan* p, int8_t* d_w, hipStream_t s) {
+  if (!p || !d_w) { set_error("NULL argument"); return FCT_EINVAL; }
+  if (!dev_ok(p)) return FCT_EINVAL;
+  if (p->nprob != 1) { set_error("entry weights are kept for single-problem plans only"); return FCT_EINVAL; }
+  const int64_t L = (int64_t)p->K * p->n;
+  if (p->gauss) FCT_HIP(hipMemcpyAsync(d_w, p->d_wsign, (size_t)L, hipMemcpyDeviceToDevice, s));
+  else FCT_HIP(hipMemsetAsync(d_w, 1, (size_t)L, s));
+  return FCT_OK;
+}
+
 fct_status fct_grid_nodes(const fct_plan* p, int32_t grid, int32_t dim, double* host_out) {
   if (!p || !host_out || grid < 0 || grid >= p->K || dim < 0 || dim >= p->grid_D[(size_t)grid]) {
     set_error("bad arguments");
@@ -780,7 +849,7 @@ void fct_ws_destroy(fct_ws* w) {
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
   dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
   dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_ring); dfree(w->d_gamma0);
-  dfree(w->d_cg); dfree(w->d_cg_part); dfree(w->d_nb8); dfree(w->d_nb_off); dfree(w->d_nb_ovf);
+  dfree(w->d_cg); dfree(w->d_cg_part); dfree(w->d_nb8); dfree(w->d_nb_off); dfree(w->d_nb_ovf); dfree(w->d_nb_diag);
   dfree(w->d_done); dfree(w->d_flags); dfree(w->d_done_tmp); dfree(w->d_state);
   dfree(w->d_state_tmp); dfree(w->d_bar); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
   dfree(w->d_outer);
@@ -811,7 +880,7 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
     if (st != FCT_OK) return st;
     // q = A c at the non-empty bins, then evaluation at the nodes
     double* q = reinterpret_cast<double*>(ws->d_rq);   // M doubles of scratch
-    FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_coeffs, q, s));
+    FCT_HIP(plan_apply_A(p, d_coeffs, q, s));
     for (const auto& lv : p->inv)
       FCT_HIP(launch_dct_level(lv, FCT_DCT_F64, FCT_ENGINE_VECTOR, q, nullptr, d_samples,
                                        p->d_emat, nullptr, p->d_bin_id, s));
@@ -986,8 +1055,8 @@ static fct_status lanczos_condition(const fct_plan* p, const double* d_v0, int32
   int steps = 0;
   for (int j = 0; j < kmax; ++j) {
     const double* vj = V + (int64_t)j * n;
-    FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, vj, q, s));
-    FCT_HIP(launch_apply_AT(p->d_cblk, p->ncblk, p->d_rowmap, q, w, s));
+    FCT_HIP(plan_apply_A(p, vj, q, s));
+    FCT_HIP(plan_apply_AT(p, q, w, s));
     for (int pass = 0; pass < 2; ++pass) {
       FCT_HIP(launch_multi_dot(V, n, j + 1, w, n, part, ldp, h, s));
       FCT_HIP(launch_orth_update(V, n, j + 1, h, w, n, s));
@@ -1073,14 +1142,14 @@ fct_status fct_select_grids(int32_t D, int64_t n, const int32_t* support, int32_
 fct_status fct_apply_A(const fct_plan* p, const double* d_c, double* d_q, hipStream_t s) {
   if (!p || !d_c || !d_q) { set_error("NULL argument"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
-  FCT_HIP(launch_apply_A(p->d_seg_off, p->d_perm, p->M, d_c, d_q, s));
+  FCT_HIP(plan_apply_A(p, d_c, d_q, s));
   return FCT_OK;
 }
 
 fct_status fct_apply_AT(const fct_plan* p, const double* d_r, double* d_s, hipStream_t s) {
   if (!p || !d_r || !d_s) { set_error("NULL argument"); return FCT_EINVAL; }
   if (!dev_ok(p)) return FCT_EINVAL;
-  FCT_HIP(launch_apply_AT(p->d_cblk, p->ncblk, p->d_rowmap, d_r, d_s, s));
+  FCT_HIP(plan_apply_AT(p, d_r, d_s, s));
   return FCT_OK;
 }
 
@@ -1090,9 +1159,12 @@ static fct_status ensure_neighbours(const fct_plan* p, fct_ws* ws, hipStream_t s
   if (ws->d_nb8) return FCT_OK;
   dfree(ws->d_nb_off);
   dfree(ws->d_nb_ovf);
+  dfree(ws->d_nb_diag);
   const int64_t n = p->n;
   FCT_HIP(dalloc(&ws->d_nb_off, n + 1, nullptr));
-  FCT_HIP(launch_cg1_count(p->d_cblk, p->ncblk, p->d_rowmap, p->d_seg_off, ws->d_nb_off, s));
+  FCT_HIP(dalloc(&ws->d_nb_diag, n, nullptr));
+  FCT_HIP(launch_cg1_count(p->d_cblk, p->ncblk, p->d_rowmap, p->d_seg_off, p->d_perm, p->d_wsign,
+                           ws->d_nb_off, ws->d_nb_diag, s));
   std::vector<int32_t> h((size_t)n + 1, 0);
   FCT_HIP(hipMemcpyAsync(h.data(), ws->d_nb_off, sizeof(int32_t) * (size_t)n,
                          hipMemcpyDeviceToHost, s));
@@ -1114,7 +1186,7 @@ static fct_status ensure_neighbours(const fct_plan* p, fct_ws* ws, hipStream_t s
   int4* nb8 = nullptr;
   FCT_HIP(dalloc(&nb8, 2 * n, nullptr));
   hipError_t e = launch_cg1_fill(p->d_cblk, p->ncblk, p->d_rowmap, p->d_seg_off, p->d_perm,
-                                 ws->d_nb_off, (int32_t)n, nb8, ws->d_nb_ovf, s);
+                                 p->d_wsign, ws->d_nb_off, (int32_t)n, nb8, ws->d_nb_ovf, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     dfree(nb8);
@@ -1312,6 +1384,14 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   if (o.tol <= 0.0) o.tol = o.mode == FCT_SOLVE_F32 ? 2e-7 : 1e-14;
   if (o.check_every > 4096) o.check_every = 4096;
   if (o.maxit > (1 << 30)) { set_error("maxit too large"); return FCT_EINVAL; }
+  if (p->gauss) {
+    if (mixed || o.single_kernel > 0) {
+      set_error("a Gauss-grid plan is solved in FP64 by the one-reduction CG "
+                "(no FP32 modes, no single kernel)");
+      return FCT_EINVAL;
+    }
+    o.one_reduction = 1;
+  }
   if (o.one_reduction != 0 &&
       (mixed || p->nprob != 1 || o.single_kernel > 0 || !ws->d_cg)) {
     set_error("one_reduction needs an FP64 solve of a single-problem plan (two-kernel form)");
@@ -1341,6 +1421,7 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     a.nb8 = ws->d_nb8;
     a.nb_off = ws->d_nb_off;
     a.nb_ovf = ws->d_nb_ovf;
+    a.nb_diag = ws->d_nb_diag;
     a.cg1_n = (int32_t)p->n;
     a.cg1_K = p->K;
     a.cg1_nblk = (int32_t)ceil_div(p->n, kCg1Block);
@@ -1366,7 +1447,8 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   int total_queued = 0, last_queued = 0;
   if (!mixed) {
     a.tol2 = o.tol * o.tol;
-    FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
+    if (p->gauss) FCT_HIP(launch_gauss_init(a, p->d_wsign, d_b, p->M, o.warm_start != 0, s));
+    else FCT_HIP(launch_cgls_init(a, d_b, o.warm_start != 0, s));
     if (a.cg1) FCT_HIP(launch_cg1_init(a, s));
     st = cgls_loop(p, ws, a, 0, o.maxit, chunk, o.use_graph != 0, fused, s, &last_queued);
     if (st != FCT_OK) return st;

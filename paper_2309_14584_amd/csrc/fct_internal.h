@@ -73,9 +73,10 @@ inline __host__ __device__ int64_t mat_offset(int N) {
 // ---- kernel launchers (each enqueues on `stream`, returns hipError_t) ----
 
 // plan construction
+// wsign (Gauss plans, else nullptr): weight in {-1, 0, 1} of every entry
 hipError_t launch_alias(const int32_t* S, const int32_t* grids, const int64_t* strides,
                         int D, int64_t n, int K, int64_t* alias, uint64_t* keys,
-                        int32_t* vals, hipStream_t s);
+                        int32_t* vals, int8_t* wsign, hipStream_t s);
 hipError_t launch_sort(uint64_t* keys, int32_t* vals, uint64_t* keys_tmp,
                        int32_t* vals_tmp, int64_t L, bool* result_in_tmp, hipStream_t s);
 hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
@@ -83,8 +84,9 @@ hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
                            int32_t* perm, int32_t* seg_off, int64_t* bin_id,
                            int32_t* rowmap, int32_t* row_off, int K, hipStream_t s);
 // cmat32: the forward matrices rounded to FP32 (the FP32 DCT mode's operands)
+// gauss: Chebyshev-Gauss nodes and the DCT-II instead of Lobatto and DCT-I
 hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, float* cmat32, double* emat,
-                         hipStream_t s);
+                         int gauss, hipStream_t s);
 // ell[r] = first four entries of row r's run in perm, -1 padded; a row with
 // more than four entries stores -(2 + t) in the last slot, t = perm index
 // where its remaining entries continue
@@ -252,6 +254,7 @@ struct CglsArgs {
   const int4* nb8;
   const int32_t* nb_off;
   const int32_t* nb_ovf;
+  const int32_t* nb_diag;   // [n] diagonal of A^T A
   int32_t cg1_n;      // columns
   int32_t cg1_K;      // grids
   int32_t cg1_nblk;   // one-wave workgroups (kCg1Block columns each)
@@ -264,11 +267,24 @@ hipError_t launch_cg1_init(const CglsArgs& a, hipStream_t s);
 // neighbour lists of a single-problem plan: counts (other members over the
 // K rows of each column) into cnt[n], then the lists from the overflow
 // offsets off[n+1] (entries beyond the eighth)
+// (w: entry weights of a Gauss plan, else nullptr; diag[n] gets the
+// diagonal of A^T A)
 hipError_t launch_cg1_count(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
-                            const int32_t* seg_off, int32_t* cnt, hipStream_t s);
+                            const int32_t* seg_off, const int32_t* perm, const int8_t* w,
+                            int32_t* cnt, int32_t* diag, hipStream_t s);
 hipError_t launch_cg1_fill(const ColBlock* cblk, int64_t ncblk, const int32_t* rowmap,
-                           const int32_t* seg_off, const int32_t* perm, const int32_t* off,
-                           int32_t n, int4* nb8, int32_t* ovf, hipStream_t s);
+                           const int32_t* seg_off, const int32_t* perm, const int8_t* w,
+                           const int32_t* off, int32_t n, int4* nb8, int32_t* ovf,
+                           hipStream_t s);
+// A c and A^T r of a Gauss plan (entry weights w [K][n]), and the start of
+// its solve: r_0 = b - A c_0 into a.r64, s_0 = A^T r_0 into a.ps.y, state reset
+hipError_t launch_apply_A_signed(const int32_t* seg_off, const int32_t* perm, const int8_t* w,
+                                 int64_t M, int64_t n, const double* c, double* q,
+                                 hipStream_t s);
+hipError_t launch_apply_AT_signed(const int32_t* rowmap, const int8_t* w, int32_t K, int64_t n,
+                                  const double* r, double* out, hipStream_t s);
+hipError_t launch_gauss_init(const CglsArgs& a, const int8_t* w, const double* b, int64_t M,
+                             bool warm, hipStream_t s);
 hipError_t launch_cg1_iter(const CglsArgs& a, int rel, hipStream_t s);
 hipError_t launch_cg1_gamma(const CglsArgs& a, int k, hipStream_t s);
 hipError_t launch_cgls_iter(const CglsArgs& a, int rel, hipStream_t s);
@@ -316,6 +332,7 @@ struct fct_plan {
   int64_t max_points = 0;
   int32_t maxdeg = 0;
   int32_t smax = 0;                // largest support entry (single problem)
+  int32_t gauss = 0;               // Gauss grids / DCT-II operator (single problem)
   std::vector<int32_t> grid_D;     // [K] dimension of each grid's problem
   std::vector<int64_t> grid_goff;  // [K+1] offsets of each grid's degrees in `grids`
   std::vector<int32_t> grids;      // degrees, grid after grid
@@ -329,6 +346,7 @@ struct fct_plan {
   int32_t* d_support = nullptr;    // [n][D]      (single problem only)
   int64_t* d_strides = nullptr;    // [K][D]      (single problem only)
   int64_t* d_alias = nullptr;      // [K*n]       (single problem only)
+  int8_t* d_wsign = nullptr;       // [K*n]       entry weights of a Gauss plan
   int32_t* d_grids = nullptr;      // degrees, as `grids`
   int64_t* d_point_off = nullptr;  // [K+1]
   fct::SampleDesc* d_sdesc = nullptr;  // [K] sampler split of each grid (single problem)
@@ -383,6 +401,7 @@ struct fct_ws {
   int4* d_nb8 = nullptr;           // [2][n] neighbour lists (built on first use)
   int32_t* d_nb_off = nullptr;     // [n+1]
   int32_t* d_nb_ovf = nullptr;     // [max(1, overflow entries)]
+  int32_t* d_nb_diag = nullptr;    // [n]
   double* d_ring = nullptr;        // [nprob][8]
   double* d_gamma0 = nullptr;      // [nprob]
   int32_t* d_done = nullptr;       // [nprob]

@@ -19,17 +19,41 @@ __device__ __forceinline__ int64_t fold_dev(int64_t a, int32_t N) {
   return r < p - r ? r : p - r;
 }
 
+// Gauss grid of N + 1 nodes (Lemma 3.1): T_a equals s T_m on the nodes with
+// r = a mod 2(N+1), m = min(r, 2(N+1) - r), s = (-1)^(a div 2(N+1)) for
+// r <= N + 1 and its negation beyond; m = N + 1 is the vanishing T_{N+1}
+// (weight 0; the entry is kept in bin m = N so that every column still has
+// one entry per grid, and adds nothing).
+__device__ __forceinline__ int64_t fold_gauss_dev(int64_t a, int32_t N, int& w) {
+  const int64_t g = (int64_t)N + 1;
+  const int64_t p = 2 * g;
+  const int64_t r = a % p;
+  const int odd = (int)((a / p) & 1);
+  if (r == g) { w = 0; return N; }
+  if (r < g) { w *= odd ? -1 : 1; return r; }
+  w *= odd ? 1 : -1;
+  return p - r;
+}
+
 __global__ __launch_bounds__(kBlock) void alias_kernel(
     const int32_t* __restrict__ S, const int32_t* __restrict__ grids,
     const int64_t* __restrict__ strides, int D, int64_t n, int K,
-    int64_t* __restrict__ alias, uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    int64_t* __restrict__ alias, uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+    int8_t* __restrict__ wsign) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)K * n) return;
   const int l = (int)(t / n);
   const int64_t j = t - (int64_t)l * n;
   int64_t bin = 0;
-  for (int i = 0; i < D; ++i)
-    bin += fold_dev(S[j * D + i], grids[l * D + i]) * strides[(int64_t)l * D + i];
+  if (wsign) {
+    int w = 1;
+    for (int i = 0; i < D; ++i)
+      bin += fold_gauss_dev(S[j * D + i], grids[l * D + i], w) * strides[(int64_t)l * D + i];
+    wsign[t] = (int8_t)w;
+  } else {
+    for (int i = 0; i < D; ++i)
+      bin += fold_dev(S[j * D + i], grids[l * D + i]) * strides[(int64_t)l * D + i];
+  }
   alias[t] = bin;
   keys[t] = ((uint64_t)l << kKeyBinBits) | (uint64_t)bin;
   vals[t] = (int32_t)j;
@@ -220,16 +244,26 @@ __global__ __launch_bounds__(kBlock) void segment_write_kernel(
 //                     g_0 = g_N = 1/2, else 1);
 //   emat[N][k][m]   = cos(pi (m k mod 2N) / N) = T_m(x_k), its inverse.
 // Degree 0 is the 1x1 identity and the single node x = 1.
+// Gauss grids (Sec. 2, eq. chebyshev_grid; the quadrature of Sec. 3.1 with
+// rows n >= 1 doubled):
+//   nodes[N*64 + k] = cos(pi (k + 1/2) / (N + 1)) = sin(pi (N - 2k) / (2 (N + 1)));
+//   cmat[N][m][k]   = (g_m 2 / (N + 1)) cos(pi (m (2k + 1) mod 4(N+1)) / (2 (N + 1))),
+//                     g_0 = 1/2, else 1 (the interpolation-normalised DCT-II);
+//   emat[N][k][m]   = cos(pi (m (2k + 1) mod 4(N+1)) / (2 (N + 1))) = T_m(x_k).
+// Degree 0 is then the single node x = 0 with the 1x1 identity.
 __global__ __launch_bounds__(kBlock) void tables_kernel(int maxdeg, double* __restrict__ nodes,
                                                         double* __restrict__ cmat,
                                                         float* __restrict__ cmat32,
-                                                        double* __restrict__ emat) {
+                                                        double* __restrict__ emat, int gauss) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = mat_offset(maxdeg + 1);
   if (t < (int64_t)(maxdeg + 1) * 64) {
     const int N = (int)(t / 64), k = (int)(t % 64);
     double x = 0.0;
-    if (k <= N) x = (N == 0) ? 1.0 : sinpi((double)(N - 2 * k) / (2.0 * N));
+    if (k <= N) {
+      if (gauss) x = sinpi((double)(N - 2 * k) / (2.0 * (N + 1)));
+      else x = (N == 0) ? 1.0 : sinpi((double)(N - 2 * k) / (2.0 * N));
+    }
     nodes[t] = x;
   }
   if (t >= total) return;
@@ -238,6 +272,17 @@ __global__ __launch_bounds__(kBlock) void tables_kernel(int maxdeg, double* __re
   const int64_t local = t - mat_offset(N);
   const int e = N + 1;
   const int row = (int)(local / e), col = (int)(local % e);
+  if (gauss) {
+    // cmat row = m, col = k; emat row = k, col = m
+    const int64_t g = (int64_t)N + 1;
+    const int64_t red = ((int64_t)row * (2 * col + 1)) % (4 * g);
+    const int64_t red_e = ((int64_t)col * (2 * row + 1)) % (4 * g);
+    const double sc = (row == 0 ? 1.0 : 2.0) / (double)g;
+    cmat[t] = sc * cospi((double)red / (double)(2 * g));
+    cmat32[t] = (float)cmat[t];
+    emat[t] = cospi((double)red_e / (double)(2 * g));
+    return;
+  }
   if (N == 0) {
     cmat[t] = 1.0;
     cmat32[t] = 1.0f;
@@ -347,10 +392,10 @@ hipError_t launch_ell(const int32_t* seg_off, const int32_t* perm, int64_t M, in
 
 hipError_t launch_alias(const int32_t* S, const int32_t* grids, const int64_t* strides,
                         int D, int64_t n, int K, int64_t* alias, uint64_t* keys,
-                        int32_t* vals, hipStream_t s) {
+                        int32_t* vals, int8_t* wsign, hipStream_t s) {
   const int64_t L = (int64_t)K * n;
   hipLaunchKernelGGL(alias_kernel, dim3((unsigned)ceil_div(L, kBlock)), dim3(kBlock), 0, s,
-                     S, grids, strides, D, n, K, alias, keys, vals);
+                     S, grids, strides, D, n, K, alias, keys, vals, wsign);
   return hipGetLastError();
 }
 
@@ -393,12 +438,12 @@ hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
 }
 
 hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, float* cmat32, double* emat,
-                         hipStream_t s) {
+                         int gauss, hipStream_t s) {
   int64_t total = mat_offset(maxdeg + 1);
   const int64_t nn = (int64_t)(maxdeg + 1) * 64;
   if (nn > total) total = nn;
   hipLaunchKernelGGL(tables_kernel, dim3((unsigned)ceil_div(total, kBlock)), dim3(kBlock), 0, s,
-                     maxdeg, nodes, cmat, cmat32, emat);
+                     maxdeg, nodes, cmat, cmat32, emat, gauss);
   return hipGetLastError();
 }
 

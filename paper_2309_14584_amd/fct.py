@@ -27,11 +27,12 @@ _lib = ctypes.CDLL(LIB_PATH)
 # status codes (include/fct.h)
 FCT_OK, FCT_EINVAL, FCT_ENOMEM, FCT_EDEVICE, FCT_ERANK, FCT_ENOCONV, FCT_ENONFINITE = range(7)
 FCT_PLAN_ALLOW_RANK_DEFICIENT = 1
+FCT_PLAN_GAUSS = 2
 
 FAMILY_PLANTED, FAMILY_EXPCOS, FAMILY_GAUSS, FAMILY_RUNGE, FAMILY_OSC = range(5)
 DCT_F64, DCT_F32, DCT_BF16X3 = 0, 1, 2
 ENGINE_VECTOR, ENGINE_MATRIX = 0, 1
-ABI_VERSION = 2          # FCT_ABI_VERSION of the header this binding follows
+ABI_VERSION = 3          # FCT_ABI_VERSION of the header this binding follows
 SOLVE_F64, SOLVE_F32_REFINE, SOLVE_F32 = 0, 1, 2
 
 _vp = ctypes.c_void_p
@@ -88,6 +89,7 @@ _plan_get_info = _sig("fct_plan_get_info", ctypes.c_int, _vp, ctypes.POINTER(Pla
 _plan_grid = _sig("fct_plan_grid", ctypes.c_int, _vp, _i32, ctypes.POINTER(_i64),
                   ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64))
 _plan_export = _sig("fct_plan_export", ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_plan_weights = _sig("fct_plan_weights", ctypes.c_int, _vp, _vp, _vp)
 _grid_nodes = _sig("fct_grid_nodes", ctypes.c_int, _vp, _i32, _i32, _vp)
 _ws_create = _sig("fct_ws_create", ctypes.c_int, _vp, ctypes.POINTER(_vp))
 _ws_destroy = _sig("fct_ws_destroy", None, _vp)
@@ -115,7 +117,8 @@ EXPORTED = ["fct_last_error", "fct_status_string", "fct_abi_version", "fct_plan_
             "fct_grid_nodes", "fct_ws_create", "fct_ws_destroy", "fct_sample", "fct_dct",
             "fct_dct_full", "fct_apply_A", "fct_apply_AT", "fct_solve", "fct_batch_create",
             "fct_plan_problem", "fct_ws_problem_info", "fct_plan_tune",
-            "fct_plan_set_dct_engine", "fct_eval", "fct_plan_condition", "fct_select_grids"]
+            "fct_plan_set_dct_engine", "fct_eval", "fct_plan_condition", "fct_select_grids",
+            "fct_plan_weights"]
 
 
 def _cond_dict(info):
@@ -224,10 +227,11 @@ class Workspace:
 
 
 class Plan:
-    """Alias structure of a support on K Lobatto grids (fct_plan_create)."""
+    """Alias structure of a support on K Lobatto grids, or with gauss=True on
+    K Chebyshev-Gauss grids with the DCT-II (fct_plan_create)."""
 
     def __init__(self, support=None, grids=None, allow_rank_deficient=False, stream=None,
-                 _handle=None):
+                 _handle=None, gauss=False):
         if _handle is not None:
             self._h = _handle
             self.support = self.grids = None
@@ -240,6 +244,8 @@ class Plan:
         self.support, self.grids = S, G
         h = _vp()
         flags = FCT_PLAN_ALLOW_RANK_DEFICIENT if allow_rank_deficient else 0
+        if gauss:
+            flags |= FCT_PLAN_GAUSS
         _check(_plan_create(S.shape[1], S.shape[0], S.ctypes.data_as(_vp), G.shape[0],
                             G.ctypes.data_as(_vp), flags, _stream(stream), ctypes.byref(h)))
         self._h = h
@@ -350,6 +356,14 @@ class Plan:
                             _stream(stream)))
         return dict(alias=alias.view(self.K, self.n), perm=perm.view(self.K, self.n),
                     seg_off=seg, bin_id=bins[: self.M], rowmap=rowmap.view(self.K, self.n))
+
+    def weights(self, stream=None):
+        """Entry weights of A, int8 [K, n] on the device (fct_plan_weights)."""
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        w = torch.empty(self.K * self.n, dtype=torch.int8, device=dev)
+        _check(_plan_weights(self._h, _vp(w.data_ptr()), _stream(stream)))
+        return w.view(self.K, self.n)
 
     def _empty(self, n):
         torch = _torch()

@@ -33,7 +33,7 @@ def test_header_symbols_exported(fct):
 
 
 def test_abi_version_and_strings(fct):
-    assert fct.abi_version() == fct.ABI_VERSION == 2
+    assert fct.abi_version() == fct.ABI_VERSION == 3
     assert fct._status_string(fct.FCT_ERANK) == b"FCT_ERANK"
     assert fct._status_string(99) == b"FCT_UNKNOWN"
 
@@ -78,3 +78,19 @@ def test_python_binding_refuses_missing_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", "import paper_2309_14584_amd.fct"],
                        cwd=tmp_path, capture_output=True, text=True)
     assert r.returncode != 0 and "libfct is not built" in r.stderr
+
+
+def test_gauss_rank_precheck_and_flags(fct):
+    """Host checks of a Gauss-grid plan (before any device work): T_{N+1}
+    vanishing on every grid, degrees equal up to sign, unknown flags."""
+    G = fct.FCT_PLAN_GAUSS
+    st, msg, _ = _create(fct, np.array([[0], [3]]), np.array([[2], [2]]), G)
+    assert st == fct.FCT_ERANK and "vanishes" in msg
+    st, msg, _ = _create(fct, np.arange(4)[:, None], np.array([[1], [1]]), G)
+    assert st == fct.FCT_ERANK
+    # grids N = 0 (node x = 0) and N = 1: T_3 = -T_1 on both (T_1 and T_3
+    # vanish at x = 0), so degree 3 repeats degree 1 up to sign
+    st, msg, _ = _create(fct, np.arange(4)[:, None], np.array([[0], [1]]), G)
+    assert st == fct.FCT_ERANK and "degree 3" in msg and "up to sign" in msg
+    st, msg, _ = _create(fct, np.array([[0], [1]]), np.array([[3]]), 8)
+    assert st == fct.FCT_EINVAL and "flags" in msg
