@@ -321,6 +321,45 @@ def bench_sparse(fct, torch, sizes=(1_000_000, 10_000_000), steps=2):
             "runs": out}
 
 
+def bench_gauss(fct, torch, steps=10):
+    """The paper's literal operator (Gauss grids, DCT-II, signed aliasing):
+    the D=6, |n|_1 <= 12 support (18,564 coefficients) on 8 Gauss grids
+    N_i ~ U{4..8}, planted coefficients.  One step = sample (inverse DCT of
+    the planted expansion) -> DCT-II -> FP64 solve (one-reduction CG); the
+    same support on Lobatto grids of the same degrees beside it."""
+    import workloads as W
+    prob = W.small_problem(41, 6, 12, 4, 8, 8)
+    ct = torch.tensor(prob.coeffs, dtype=torch.float64, device="cuda")
+    out = {"workload": f"{prob.name}: D=6, |n|_1<=12, 8 grids N_i ~ U{{4..8}}, planted"}
+    for name, gauss in (("gauss", True), ("lobatto_same_grids", False)):
+        plan = fct.Plan(prob.support, prob.grids, gauss=gauss)
+        smp = torch.empty(plan.P, dtype=torch.float64, device="cuda")
+        b = torch.empty(plan.M, dtype=torch.float64, device="cuda")
+        c = torch.empty(plan.n, dtype=torch.float64, device="cuda")
+
+        def step():
+            plan.sample(fct.FAMILY_PLANTED, coeffs=ct, out=smp)
+            plan.dct(smp, out=b)
+            return plan.solve(b, out=c)[1]
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        err = float(np.max(np.abs(c.cpu().numpy() - prob.coeffs)) / np.max(np.abs(prob.coeffs)))
+        tinfo = plan.solve(b, out=c, timing=True)[1]
+        out[name] = {"points": plan.P, "rows": plan.M, "ms_per_step": 1e3 * dt,
+                     "iterations": info.iterations, "max_rel_err": err,
+                     "solver": "one_reduction" if gauss else "cgls",
+                     "kernel_us_per_iteration": tinfo.rows_kernel_us + tinfo.cols_kernel_us,
+                     "recovered_coeffs_per_s": prob.n / dt if err <= TOL else 0.0}
+        plan.close()
+    return out
+
+
 def bench_serving(fct, torch, duration, rate=200.0, slots=4):
     """The serving workload: requests drawn (seeded) from a pool of 64 jobs
     of four kinds (D2 |n|_1<=16; D6 |n|_1<=12 exp-cos; a batched-workload
@@ -397,7 +436,7 @@ def main():
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-precision", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=3)
-    ap.add_argument("--only", choices=["batched", "serving", "precision", "sparse"],
+    ap.add_argument("--only", choices=["batched", "serving", "precision", "sparse", "gauss"],
                     help="run one sub-workload alone and print its JSON (for profiling)")
     ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--skip-sparse", action="store_true",
@@ -437,6 +476,9 @@ def main():
         return
     if args.only == "serving":
         print(json.dumps({"serving": bench_serving(fct, torch, args.serving_seconds)}), flush=True)
+        return
+    if args.only == "gauss":
+        print(json.dumps({"gauss_operator": bench_gauss(fct, torch)}), flush=True)
         return
     prob = W.config2()
     c_gold = np.load(os.path.join(ROOT, "tests", "golden", "cfg2_coeffs_qr.npy"))
@@ -535,6 +577,7 @@ def main():
                        "eval_terms_per_s": 5000 * prob.n / t_eval}
     plan.close()
     out["grid_selection"] = bench_grid_selection(fct, torch, prob)
+    out["gauss_operator"] = bench_gauss(fct, torch)
     if not args.skip_sparse:
         out["sparse_recovery"] = bench_sparse(fct, torch)
     if not args.skip_batched:
