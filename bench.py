@@ -439,6 +439,8 @@ def main():
     ap.add_argument("--only", choices=["batched", "serving", "precision", "sparse", "gauss"],
                     help="run one sub-workload alone and print its JSON (for profiling)")
     ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--skip-gauss", action="store_true",
+                    help="skip the Gauss-grid operator leg")
     ap.add_argument("--skip-sparse", action="store_true",
                     help="skip the D=100 sparse-support (f3) runs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -577,7 +579,8 @@ def main():
                        "eval_terms_per_s": 5000 * prob.n / t_eval}
     plan.close()
     out["grid_selection"] = bench_grid_selection(fct, torch, prob)
-    out["gauss_operator"] = bench_gauss(fct, torch)
+    if not args.skip_gauss:
+        out["gauss_operator"] = bench_gauss(fct, torch)
     if not args.skip_sparse:
         out["sparse_recovery"] = bench_sparse(fct, torch)
     if not args.skip_batched:
