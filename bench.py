@@ -311,11 +311,26 @@ def bench_sparse(fct, torch, sizes=(1_000_000, 10_000_000), steps=2):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         err = float(np.max(np.abs(c.cpu().numpy() - p.coeffs)) / np.max(np.abs(p.coeffs)))
-        out.append({"D": p.D, "N": N, "grids": p.K, "points": plan.P, "rows": plan.M,
-                    "plan_seconds": t_plan, "ms_per_step": 1e3 * dt,
-                    "iterations": info.iterations, "max_rel_err": err,
-                    "recovered_coeffs_per_s": N / dt if err <= TOL else 0.0})
+        run = {"D": p.D, "N": N, "grids": p.K, "points": plan.P, "rows": plan.M,
+               "plan_seconds": t_plan, "ms_per_step": 1e3 * dt,
+               "iterations": info.iterations, "max_rel_err": err,
+               "recovered_coeffs_per_s": N / dt if err <= TOL else 0.0}
         plan.close()
+        if N <= 1_000_000:
+            # the same job with each grid's rows ordered by first member
+            plan = fct.Plan(p.support, p.grids, allow_rank_deficient=True, rows_by_member=True)
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                info = step()
+            torch.cuda.synchronize()
+            dt2 = (time.perf_counter() - t0) / steps
+            err2 = float(np.max(np.abs(c.cpu().numpy() - p.coeffs)) / np.max(np.abs(p.coeffs)))
+            run["rows_by_member"] = {"ms_per_step": 1e3 * dt2, "iterations": info.iterations,
+                                     "max_rel_err": err2}
+            plan.close()
+        out.append(run)
         del p, ct, smp, b, c
     return {"workload": "f3: D=100, random S^inf_{8,100} supports, 20 Alg.-1 grids, planted",
             "runs": out}

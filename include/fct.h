@@ -132,6 +132,15 @@ typedef enum fct_solve_mode {
  * condition estimate and evaluation as for Lobatto plans.  N_i = 0 is the
  * single node x = 0. */
 #define FCT_PLAN_GAUSS 2u
+/* Row order for sparse supports: each grid's rows ordered by their first
+ * (smallest) support column instead of by bin, runs unchanged.  When most
+ * rows hold one entry (random high-dimensional supports) the matvecs then
+ * read p and r nearly in order instead of at random.  perm, seg_off, bin_id
+ * and rowmap (fct_plan_export) follow this order; b from fct_dct is in it
+ * (the transform writes the bins in bin order to the workspace, then gathers
+ * them), so fct_dct needs the workspace.  Single problem (not batched), not
+ * with FCT_PLAN_GAUSS. */
+#define FCT_PLAN_ROWS_BY_MEMBER 4u
 
 typedef struct fct_plan fct_plan;
 typedef struct fct_ws fct_ws;

@@ -188,7 +188,7 @@ void destroy_plan(fct_plan* p) {
   if (!p) return;
   dfree(p->d_support); dfree(p->d_grids); dfree(p->d_strides); dfree(p->d_point_off);
   dfree(p->d_alias); dfree(p->d_perm); dfree(p->d_seg_off); dfree(p->d_bin_id);
-  dfree(p->d_wsign);
+  dfree(p->d_wsign); dfree(p->d_bin_dct); dfree(p->d_row_old); dfree(p->d_row_new);
   dfree(p->d_rowmap); dfree(p->d_row_off); dfree(p->d_ell); dfree(p->d_nodes); dfree(p->d_cmat);
   dfree(p->d_emat); dfree(p->d_cmat32); dfree(p->d_rblk); dfree(p->d_cblk); dfree(p->d_prob);
   dfree(p->d_units); dfree(p->d_rblk32); dfree(p->d_ell16); dfree(p->d_sdesc);
@@ -240,8 +240,9 @@ fct_status build_dct_levels(fct_plan* p) {
   if (st != FCT_OK) return st;
   st = upload_levels(inv, p->inv, &p->device_bytes, (int32_t)tm);
   if (st != FCT_OK) return st;
-  for (const auto& L : p->fwd) FCT_HIP(launch_tile_rows(L, p->d_bin_id, nullptr));
-  for (const auto& L : p->inv) FCT_HIP(launch_tile_rows(L, p->d_bin_id, nullptr));
+  const int64_t* bins = p->d_bin_dct ? p->d_bin_dct : p->d_bin_id;   // (grid, bin) row order
+  for (const auto& L : p->fwd) FCT_HIP(launch_tile_rows(L, bins, nullptr));
+  for (const auto& L : p->inv) FCT_HIP(launch_tile_rows(L, bins, nullptr));
   int cus = 0;
   FCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
   for (auto* set : {&p->fwd, &p->fwd_full, &p->inv})
@@ -402,8 +403,12 @@ fct_status validate_inputs(int32_t D, int64_t n, const int32_t* S, int32_t K, co
         return FCT_EINVAL;
       }
   }
-  if (flags & ~(FCT_PLAN_ALLOW_RANK_DEFICIENT | FCT_PLAN_GAUSS)) {
+  if (flags & ~(FCT_PLAN_ALLOW_RANK_DEFICIENT | FCT_PLAN_GAUSS | FCT_PLAN_ROWS_BY_MEMBER)) {
     set_error("unknown plan flags 0x%x", flags);
+    return FCT_EINVAL;
+  }
+  if ((flags & FCT_PLAN_GAUSS) && (flags & FCT_PLAN_ROWS_BY_MEMBER)) {
+    set_error("FCT_PLAN_GAUSS and FCT_PLAN_ROWS_BY_MEMBER do not combine");
     return FCT_EINVAL;
   }
   if ((flags & FCT_PLAN_GAUSS) && !(flags & FCT_PLAN_ALLOW_RANK_DEFICIENT)) {
@@ -527,6 +532,7 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
 
   FCT_HIP(hipGetDevice(&p->device));
   p->gauss = (flags & FCT_PLAN_GAUSS) ? 1 : 0;
+  p->rows_by_member = (flags & FCT_PLAN_ROWS_BY_MEMBER) ? 1 : 0;
   p->nprob = 1;
   p->D = D; p->K = K; p->n = n;
   p->grids.assign(grids, grids + (size_t)K * D);
@@ -591,6 +597,39 @@ fct_status fct_plan_create(int32_t D, int64_t n, const int32_t* support, int32_t
                          hipMemcpyDeviceToHost, stream));
   FCT_HIP(hipStreamSynchronize(stream));
   p->M = p->row_off[K];
+  if (p->rows_by_member) {
+    // second stable sort by (grid, first member of the row): same rows, each
+    // grid's rows ordered by their smallest column; the (grid, bin) order
+    // stays behind for the DCT (d_bin_dct) with the map between the two
+    int32_t *perm2 = nullptr, *seg2 = nullptr, *rowmap2 = nullptr;
+    int64_t* bin2 = nullptr;
+    struct G2 {
+      int32_t **a, **b, **c; int64_t** d;
+      ~G2() { dfree(*a); dfree(*b); dfree(*c); dfree(*d); }
+    } g2{&perm2, &seg2, &rowmap2, &bin2};
+    FCT_HIP(dalloc(&perm2, L, nullptr));
+    FCT_HIP(dalloc(&seg2, L + 1, nullptr));
+    FCT_HIP(dalloc(&rowmap2, L, nullptr));
+    FCT_HIP(dalloc(&bin2, L, nullptr));
+    FCT_HIP(dalloc(&p->d_row_old, p->M, bytes));
+    FCT_HIP(launch_member_keys(p->d_rowmap, p->d_perm, p->d_seg_off, n, K, guard.k0, guard.v0,
+                               stream));
+    bool in_tmp2 = false;
+    FCT_HIP(launch_sort(guard.k0, guard.v0, guard.k1, guard.v1, L, &in_tmp2, stream));
+    FCT_HIP(launch_segments(in_tmp2 ? guard.k1 : guard.k0, in_tmp2 ? guard.v1 : guard.v0, L, n,
+                            guard.bc, nb, perm2, seg2, bin2, rowmap2, p->d_row_off, K, stream));
+    FCT_HIP(launch_row_old(perm2, seg2, p->d_rowmap, p->d_bin_id, p->M, n, p->d_row_old, bin2,
+                           stream));
+    FCT_HIP(dalloc(&p->d_row_new, p->M, bytes));
+    FCT_HIP(launch_index_inverse(p->d_row_old, p->M, p->d_row_new, stream));
+    FCT_HIP(hipStreamSynchronize(stream));
+    p->d_bin_dct = p->d_bin_id;
+    p->d_bin_id = bin2;
+    bin2 = nullptr;
+    std::swap(p->d_perm, perm2);
+    std::swap(p->d_seg_off, seg2);
+    std::swap(p->d_rowmap, rowmap2);
+  }
   FCT_HIP(dalloc(&p->d_ell, p->M, bytes));
   FCT_HIP(launch_ell(p->d_seg_off, p->d_perm, p->M, p->d_ell, stream));
   FCT_HIP(hipStreamSynchronize(stream));
@@ -633,6 +672,10 @@ fct_status fct_batch_create(int32_t count, const fct_plan* const* plans, hipStre
     const fct_plan* s = plans[q];
     if (!s || s->nprob != 1) { set_error("plan %d is NULL or already a batch", q); return FCT_EINVAL; }
     if (s->gauss) { set_error("plan %d is a Gauss-grid plan (not batched)", q); return FCT_EINVAL; }
+    if (s->rows_by_member) {
+      set_error("plan %d orders rows by first member (not batched)", q);
+      return FCT_EINVAL;
+    }
     if (s->device != dev) { set_error("plan %d lives on another device", q); return FCT_EINVAL; }
     Lsum += (int64_t)s->K * s->n;
     Msum += s->M;
@@ -818,6 +861,7 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
   FCT_HIP(hipHostMalloc((void**)&w->h_gtrue, sizeof(double) * 2 * P, hipHostMallocDefault));
   FCT_HIP(dalloc(&w->d_part_q, 4 * p->nrblk, nullptr));   // one per wave of a row block
   FCT_HIP(dalloc(&w->d_part_s, p->ncblk, nullptr));
+  if (p->rows_by_member) FCT_HIP(dalloc(&w->d_bperm, p->M, nullptr));
   if (P == 1) {
     FCT_HIP(dalloc(&w->d_cg, 2 * p->n, nullptr));
     FCT_HIP(dalloc(&w->d_cg_part, 4 * ceil_div(p->n, kCg1Block), nullptr));
@@ -849,7 +893,7 @@ void fct_ws_destroy(fct_ws* w) {
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
   dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
   dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_ring); dfree(w->d_gamma0);
-  dfree(w->d_cg); dfree(w->d_cg_part); dfree(w->d_nb8); dfree(w->d_nb_off); dfree(w->d_nb_ovf); dfree(w->d_nb_diag);
+  dfree(w->d_cg); dfree(w->d_cg_part); dfree(w->d_bperm); dfree(w->d_nb8); dfree(w->d_nb_off); dfree(w->d_nb_ovf); dfree(w->d_nb_diag);
   dfree(w->d_done); dfree(w->d_flags); dfree(w->d_done_tmp); dfree(w->d_state);
   dfree(w->d_state_tmp); dfree(w->d_bar); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
   dfree(w->d_outer);
@@ -880,10 +924,17 @@ fct_status fct_sample(const fct_plan* p, int32_t family, const double* params, i
     if (st != FCT_OK) return st;
     // q = A c at the non-empty bins, then evaluation at the nodes
     double* q = reinterpret_cast<double*>(ws->d_rq);   // M doubles of scratch
-    FCT_HIP(plan_apply_A(p, d_coeffs, q, s));
+    if (p->rows_by_member) {
+      // q in the plan's row order, then scattered to the (grid, bin) order
+      FCT_HIP(plan_apply_A(p, d_coeffs, ws->d_bperm, s));
+      FCT_HIP(launch_rows_gather(ws->d_bperm, p->d_row_new, p->M, q, s));
+    } else {
+      FCT_HIP(plan_apply_A(p, d_coeffs, q, s));
+    }
+    const int64_t* bins = p->d_bin_dct ? p->d_bin_dct : p->d_bin_id;
     for (const auto& lv : p->inv)
       FCT_HIP(launch_dct_level(lv, FCT_DCT_F64, FCT_ENGINE_VECTOR, q, nullptr, d_samples,
-                                       p->d_emat, nullptr, p->d_bin_id, s));
+                                       p->d_emat, nullptr, bins, s));
     return FCT_OK;
   }
   if (p->nprob != 1) {
@@ -930,14 +981,19 @@ fct_status fct_dct(const fct_plan* p, const double* d_samples, double* d_b, int3
   fct_status st = check_mode(p, mode);
   if (st != FCT_OK) return st;
   void* scratch = nullptr;
-  if (p->fwd.size() > 1) {
+  if (p->fwd.size() > 1 || p->rows_by_member) {
     st = check_ws(p, ws);
     if (st != FCT_OK) return st;
     scratch = ws->d_scratch;
   }
+  // rows by first member: the passes write b in (grid, bin) order, then the
+  // rows are gathered into the plan's order
+  double* out = p->rows_by_member ? ws->d_bperm : d_b;
+  const int64_t* bins = p->d_bin_dct ? p->d_bin_dct : p->d_bin_id;
   for (const auto& lv : p->fwd)
-    FCT_HIP(launch_dct_level(lv, mode, p->dct_engine[mode], d_samples, scratch, d_b,
-                                     p->d_cmat, p->d_cmat32, p->d_bin_id, s));
+    FCT_HIP(launch_dct_level(lv, mode, p->dct_engine[mode], d_samples, scratch, out,
+                                     p->d_cmat, p->d_cmat32, bins, s));
+  if (p->rows_by_member) FCT_HIP(launch_rows_gather(ws->d_bperm, p->d_row_old, p->M, d_b, s));
   return FCT_OK;
 }
 
@@ -950,7 +1006,8 @@ fct_status fct_dct_full(const fct_plan* p, const double* d_samples, double* d_ou
   if (st != FCT_OK) return st;
   for (const auto& lv : p->fwd_full)
     FCT_HIP(launch_dct_level(lv, mode, p->dct_engine[mode], d_samples, nullptr, d_out,
-                                     p->d_cmat, p->d_cmat32, p->d_bin_id, s));
+                                     p->d_cmat, p->d_cmat32,
+                                     p->d_bin_dct ? p->d_bin_dct : p->d_bin_id, s));
   return FCT_OK;
 }
 

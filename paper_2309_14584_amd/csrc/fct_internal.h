@@ -84,6 +84,20 @@ hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
                            int32_t* perm, int32_t* seg_off, int64_t* bin_id,
                            int32_t* rowmap, int32_t* row_off, int K, hipStream_t s);
 // cmat32: the forward matrices rounded to FP32 (the FP32 DCT mode's operands)
+// Rows by first member (plan flag): keys of the second sort, then each new
+// row's (grid, bin)-order index and bin; row permutations of M doubles
+// (dst[r] = src[idx[r]], and dst[idx[r]] = src[r])
+hipError_t launch_member_keys(const int32_t* rowmap, const int32_t* perm, const int32_t* seg_off,
+                             int64_t n, int K, uint64_t* keys, int32_t* vals, hipStream_t s);
+hipError_t launch_row_old(const int32_t* perm_new, const int32_t* seg_new,
+                          const int32_t* rowmap_old, const int64_t* bin_old, int64_t M, int64_t n,
+                          int32_t* row_old, int64_t* bin_new, hipStream_t s);
+hipError_t launch_rows_gather(const double* src, const int32_t* idx, int64_t M, double* dst,
+                              hipStream_t s);
+hipError_t launch_rows_scatter(const double* src, const int32_t* idx, int64_t M, double* dst,
+                               hipStream_t s);
+// inv[idx[r]] = r for a permutation idx of 0..M-1
+hipError_t launch_index_inverse(const int32_t* idx, int64_t M, int32_t* inv, hipStream_t s);
 // gauss: Chebyshev-Gauss nodes and the DCT-II instead of Lobatto and DCT-I
 hipError_t launch_tables(int maxdeg, double* nodes, double* cmat, float* cmat32, double* emat,
                          int gauss, hipStream_t s);
@@ -333,6 +347,7 @@ struct fct_plan {
   int32_t maxdeg = 0;
   int32_t smax = 0;                // largest support entry (single problem)
   int32_t gauss = 0;               // Gauss grids / DCT-II operator (single problem)
+  int32_t rows_by_member = 0;      // each grid's rows ordered by first member (single problem)
   std::vector<int32_t> grid_D;     // [K] dimension of each grid's problem
   std::vector<int64_t> grid_goff;  // [K+1] offsets of each grid's degrees in `grids`
   std::vector<int32_t> grids;      // degrees, grid after grid
@@ -347,6 +362,9 @@ struct fct_plan {
   int64_t* d_strides = nullptr;    // [K][D]      (single problem only)
   int64_t* d_alias = nullptr;      // [K*n]       (single problem only)
   int8_t* d_wsign = nullptr;       // [K*n]       entry weights of a Gauss plan
+  int64_t* d_bin_dct = nullptr;    // [M] bins in (grid, bin) row order (rows_by_member plans)
+  int32_t* d_row_old = nullptr;    // [M] (grid, bin)-order index of each row (rows_by_member)
+  int32_t* d_row_new = nullptr;    // [M] its inverse: the row of each (grid, bin)-order index
   int32_t* d_grids = nullptr;      // degrees, as `grids`
   int64_t* d_point_off = nullptr;  // [K+1]
   fct::SampleDesc* d_sdesc = nullptr;  // [K] sampler split of each grid (single problem)
@@ -402,6 +420,7 @@ struct fct_ws {
   int32_t* d_nb_off = nullptr;     // [n+1]
   int32_t* d_nb_ovf = nullptr;     // [max(1, overflow entries)]
   int32_t* d_nb_diag = nullptr;    // [n]
+  double* d_bperm = nullptr;       // [M] rows in (grid, bin) order (rows_by_member plans)
   double* d_ring = nullptr;        // [nprob][8]
   double* d_gamma0 = nullptr;      // [nprob]
   int32_t* d_done = nullptr;       // [nprob]

@@ -298,6 +298,59 @@ __global__ __launch_bounds__(kBlock) void tables_kernel(int maxdeg, double* __re
   emat[t] = cs;
 }
 
+// Rows by first member: the sort key of entry (l, j) is its grid and the
+// first (smallest) column of its row in the (grid, bin) order, so a second
+// stable sort keeps every row's run together and in ascending columns while
+// ordering each grid's rows by their first column.
+__global__ __launch_bounds__(kBlock) void member_keys_kernel(
+    const int32_t* __restrict__ rowmap, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ seg_off, int64_t n, int64_t L, uint64_t* __restrict__ keys,
+    int32_t* __restrict__ vals) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L) return;
+  const int64_t l = t / n;
+  const int32_t j = (int32_t)(t - l * n);
+  const int32_t first = perm[seg_off[rowmap[t]]];
+  keys[t] = ((uint64_t)l << kKeyBinBits) | (uint64_t)first;
+  vals[t] = j;
+}
+
+// For each row of the new order: its index in the (grid, bin) order (the
+// old row of its first member) and its bin.
+__global__ __launch_bounds__(kBlock) void row_old_kernel(
+    const int32_t* __restrict__ perm_new, const int32_t* __restrict__ seg_new,
+    const int32_t* __restrict__ rowmap_old, const int64_t* __restrict__ bin_old, int64_t M,
+    int64_t n, int32_t* __restrict__ row_old, int64_t* __restrict__ bin_new) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= M) return;
+  const int64_t t = seg_new[r];
+  const int64_t l = t / n;
+  const int32_t ro = rowmap_old[l * n + perm_new[t]];
+  row_old[r] = ro;
+  bin_new[r] = bin_old[ro];
+}
+
+__global__ __launch_bounds__(kBlock) void rows_gather_kernel(const double* __restrict__ src,
+                                                             const int32_t* __restrict__ idx,
+                                                             int64_t M, double* __restrict__ dst) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < M) dst[r] = src[idx[r]];
+}
+
+__global__ __launch_bounds__(kBlock) void index_inverse_kernel(const int32_t* __restrict__ idx,
+                                                               int64_t M,
+                                                               int32_t* __restrict__ inv) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < M) inv[idx[r]] = (int32_t)r;
+}
+
+__global__ __launch_bounds__(kBlock) void rows_scatter_kernel(const double* __restrict__ src,
+                                                              const int32_t* __restrict__ idx,
+                                                              int64_t M, double* __restrict__ dst) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < M) dst[idx[r]] = src[r];
+}
+
 __global__ __launch_bounds__(kBlock) void ell_kernel(const int32_t* __restrict__ seg_off,
                                                      const int32_t* __restrict__ perm, int64_t M,
                                                      int4* __restrict__ ell) {
@@ -434,6 +487,46 @@ hipError_t launch_segments(const uint64_t* keys, const int32_t* vals, int64_t L,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(segment_write_kernel, dim3((unsigned)nblocks), dim3(kBlock), 0, s, keys,
                      vals, L, n, block_counts, perm, seg_off, bin_id, rowmap, row_off, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_member_keys(const int32_t* rowmap, const int32_t* perm, const int32_t* seg_off,
+                             int64_t n, int K, uint64_t* keys, int32_t* vals, hipStream_t s) {
+  const int64_t L = (int64_t)K * n;
+  hipLaunchKernelGGL(member_keys_kernel, dim3((unsigned)ceil_div(L, kBlock)), dim3(kBlock), 0, s,
+                     rowmap, perm, seg_off, n, L, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_old(const int32_t* perm_new, const int32_t* seg_new,
+                          const int32_t* rowmap_old, const int64_t* bin_old, int64_t M, int64_t n,
+                          int32_t* row_old, int64_t* bin_new, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_old_kernel, dim3((unsigned)ceil_div(M, kBlock)), dim3(kBlock), 0, s,
+                     perm_new, seg_new, rowmap_old, bin_old, M, n, row_old, bin_new);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_gather(const double* src, const int32_t* idx, int64_t M, double* dst,
+                              hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rows_gather_kernel, dim3((unsigned)ceil_div(M, kBlock)), dim3(kBlock), 0, s,
+                     src, idx, M, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_index_inverse(const int32_t* idx, int64_t M, int32_t* inv, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(index_inverse_kernel, dim3((unsigned)ceil_div(M, kBlock)), dim3(kBlock), 0,
+                     s, idx, M, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_scatter(const double* src, const int32_t* idx, int64_t M, double* dst,
+                               hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rows_scatter_kernel, dim3((unsigned)ceil_div(M, kBlock)), dim3(kBlock), 0,
+                     s, src, idx, M, dst);
   return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 FCT_OK, FCT_EINVAL, FCT_ENOMEM, FCT_EDEVICE, FCT_ERANK, FCT_ENOCONV, FCT_ENONFINITE = range(7)
 FCT_PLAN_ALLOW_RANK_DEFICIENT = 1
 FCT_PLAN_GAUSS = 2
+FCT_PLAN_ROWS_BY_MEMBER = 4
 
 FAMILY_PLANTED, FAMILY_EXPCOS, FAMILY_GAUSS, FAMILY_RUNGE, FAMILY_OSC = range(5)
 DCT_F64, DCT_F32, DCT_BF16X3 = 0, 1, 2
@@ -231,7 +232,7 @@ class Plan:
     K Chebyshev-Gauss grids with the DCT-II (fct_plan_create)."""
 
     def __init__(self, support=None, grids=None, allow_rank_deficient=False, stream=None,
-                 _handle=None, gauss=False):
+                 _handle=None, gauss=False, rows_by_member=False):
         if _handle is not None:
             self._h = _handle
             self.support = self.grids = None
@@ -246,6 +247,8 @@ class Plan:
         flags = FCT_PLAN_ALLOW_RANK_DEFICIENT if allow_rank_deficient else 0
         if gauss:
             flags |= FCT_PLAN_GAUSS
+        if rows_by_member:
+            flags |= FCT_PLAN_ROWS_BY_MEMBER
         _check(_plan_create(S.shape[1], S.shape[0], S.ctypes.data_as(_vp), G.shape[0],
                             G.ctypes.data_as(_vp), flags, _stream(stream), ctypes.byref(h)))
         self._h = h

@@ -94,3 +94,10 @@ def test_gauss_rank_precheck_and_flags(fct):
     assert st == fct.FCT_ERANK and "degree 3" in msg and "up to sign" in msg
     st, msg, _ = _create(fct, np.array([[0], [1]]), np.array([[3]]), 8)
     assert st == fct.FCT_EINVAL and "flags" in msg
+
+
+def test_rows_by_member_flag_checks(fct):
+    S = np.array([[0, 0], [1, 0], [0, 1]])
+    st, msg, _ = _create(fct, S, np.array([[3, 3]]),
+                         fct.FCT_PLAN_GAUSS | fct.FCT_PLAN_ROWS_BY_MEMBER)
+    assert st == fct.FCT_EINVAL and "combine" in msg
