@@ -866,19 +866,18 @@ fct_status fct_ws_create(const fct_plan* p, fct_ws** out) {
     FCT_HIP(dalloc(&w->d_cg, 2 * p->n, nullptr));
     FCT_HIP(dalloc(&w->d_cg_part, 4 * ceil_div(p->n, kCg1Block), nullptr));
   }
-  FCT_HIP(dalloc(&w->d_ring, 8 * P, nullptr));
-  FCT_HIP(dalloc(&w->d_gamma0, P, nullptr));
-  FCT_HIP(dalloc(&w->d_done, P, nullptr));
-  FCT_HIP(dalloc(&w->d_flags, P, nullptr));
+  FCT_HIP(dalloc(&w->d_status, (int64_t)status_bytes(P), nullptr));
+  {
+    const StatusView v = status_view(w->d_status, P);
+    w->d_ring = v.ring; w->d_gamma0 = v.gamma0; w->d_done = v.done; w->d_flags = v.flags;
+  }
   FCT_HIP(dalloc(&w->d_done_tmp, P, nullptr));
   FCT_HIP(dalloc(&w->d_state, 4, nullptr));
   FCT_HIP(dalloc(&w->d_state_tmp, 4, nullptr));
   FCT_HIP(dalloc(&w->d_bar, 4, nullptr));
   FCT_HIP(hipMemset(w->d_bar, 0, sizeof(int32_t) * 4));
-  FCT_HIP(hipHostMalloc((void**)&w->h_done, sizeof(int32_t) * 3 * P, hipHostMallocDefault));
-  FCT_HIP(hipHostMalloc((void**)&w->h_ring, sizeof(double) * 3 * 8 * P, hipHostMallocDefault));
-  FCT_HIP(hipHostMalloc((void**)&w->h_gamma0, sizeof(double) * 3 * P, hipHostMallocDefault));
-  FCT_HIP(hipHostMalloc((void**)&w->h_flags, sizeof(int32_t) * P, hipHostMallocDefault));
+  FCT_HIP(hipHostMalloc((void**)&w->h_status, 3 * status_bytes(P), hipHostMallocDefault));
+  w->h_flags = status_view(w->h_status + 2 * status_bytes(P), P).flags;
   for (auto& e : w->ev) FCT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   FCT_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
   guard.w = nullptr;
@@ -892,19 +891,16 @@ void fct_ws_destroy(fct_ws* w) {
   if (w->graph_stream) (void)hipStreamDestroy(w->graph_stream);
   for (auto& e : w->ev) if (e) (void)hipEventDestroy(e);
   dfree(w->d_scratch); dfree(w->d_rq); dfree(w->d_ps); dfree(w->d_ctmp);
-  dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_ring); dfree(w->d_gamma0);
+  dfree(w->d_part_q); dfree(w->d_part_s); dfree(w->d_status);
   dfree(w->d_cg); dfree(w->d_cg_part); dfree(w->d_bperm); dfree(w->d_nb8); dfree(w->d_nb_off); dfree(w->d_nb_ovf); dfree(w->d_nb_diag);
-  dfree(w->d_done); dfree(w->d_flags); dfree(w->d_done_tmp); dfree(w->d_state);
+  dfree(w->d_done_tmp); dfree(w->d_state);
   dfree(w->d_state_tmp); dfree(w->d_bar); dfree(w->d_r64); dfree(w->d_part_true); dfree(w->d_gtrue);
   dfree(w->d_outer);
   if (w->h_outer) (void)hipHostFree(w->h_outer);
   dfree(w->d_gprev);
   if (w->h_gprev) (void)hipHostFree(w->h_gprev);
   if (w->h_gtrue) (void)hipHostFree(w->h_gtrue);
-  if (w->h_done) (void)hipHostFree(w->h_done);
-  if (w->h_ring) (void)hipHostFree(w->h_ring);
-  if (w->h_gamma0) (void)hipHostFree(w->h_gamma0);
-  if (w->h_flags) (void)hipHostFree(w->h_flags);
+  if (w->h_status) (void)hipHostFree(w->h_status);
   delete w;
 }
 
@@ -1340,12 +1336,9 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
       queued += c;
       const int sl = (head + inflight) & 1;
       upto[sl] = queued;
-      FCT_HIP(hipMemcpyAsync(ws->h_done + (size_t)sl * P, a.done, sizeof(int32_t) * P,
-                             hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(ws->h_ring + (size_t)sl * 8 * P, a.ring, sizeof(double) * 8 * P,
-                             hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(ws->h_gamma0 + (size_t)sl * P, a.gamma0, sizeof(double) * P,
-                             hipMemcpyDeviceToHost, s));
+      // ring, gamma0 and done of every problem in one copy
+      FCT_HIP(hipMemcpyAsync(ws->h_status + (size_t)sl * status_bytes(P), ws->d_status,
+                             (size_t)76 * P, hipMemcpyDeviceToHost, s));
       FCT_HIP(hipEventRecord(ws->ev[sl], s));
       ++inflight;
     }
@@ -1354,9 +1347,10 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
     FCT_HIP(hipEventSynchronize(ws->ev[sl]));
     head ^= 1;
     --inflight;
-    const int32_t* hd = ws->h_done + (size_t)sl * P;
-    const double* hr = ws->h_ring + (size_t)sl * 8 * P;
-    const double* hg0 = ws->h_gamma0 + (size_t)sl * P;
+    const StatusView hv = status_view(ws->h_status + (size_t)sl * status_bytes(P), P);
+    const int32_t* hd = hv.done;
+    const double* hr = hv.ring;
+    const double* hg0 = hv.gamma0;
     const int k = k0 + upto[sl] - 1;             // last iteration of that chunk
     bool all_done = true;
     int need_max = -1;
@@ -1498,9 +1492,10 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   if (fused > 0) FCT_HIP(launch_fill_i32(ws->d_bar, 4, 0, s));
 
   std::vector<int> iters((size_t)P, 0), rounds((size_t)P, 0);
-  int32_t* fd = ws->h_done + (size_t)2 * P;
-  double* fr = ws->h_ring + (size_t)2 * 8 * P;
-  double* fg0 = ws->h_gamma0 + (size_t)2 * P;
+  const StatusView fin = status_view(ws->h_status + 2 * status_bytes(P), P);
+  int32_t* fd = fin.done;
+  double* fr = fin.ring;
+  double* fg0 = fin.gamma0;
   int total_queued = 0, last_queued = 0;
   if (!mixed) {
     a.tol2 = o.tol * o.tol;
@@ -1510,15 +1505,11 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
     st = cgls_loop(p, ws, a, 0, o.maxit, chunk, o.use_graph != 0, fused, s, &last_queued);
     if (st != FCT_OK) return st;
     total_queued = last_queued;
-    FCT_HIP(hipMemcpyAsync(fd, a.done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
-    FCT_HIP(hipStreamSynchronize(s));
-    bool any_running = false;
-    for (int q = 0; q < P; ++q) any_running |= fd[q] == 0;
-    if (any_running)
-      FCT_HIP(a.cg1 ? launch_cg1_gamma(a, last_queued, s) : launch_cgls_gamma(a, last_queued, s));
-    FCT_HIP(hipMemcpyAsync(fr, a.ring, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, s));
-    FCT_HIP(hipMemcpyAsync(fg0, a.gamma0, sizeof(double) * P, hipMemcpyDeviceToHost, s));
-    FCT_HIP(hipMemcpyAsync(ws->h_flags, a.flags, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+    // gamma of the last queued iteration into the ring of every problem that
+    // has not stopped (the kernel checks done itself), then the final status
+    FCT_HIP(a.cg1 ? launch_cg1_gamma(a, last_queued, s) : launch_cgls_gamma(a, last_queued, s));
+    FCT_HIP(hipMemcpyAsync(ws->h_status + 2 * status_bytes(P), ws->d_status, status_bytes(P),
+                           hipMemcpyDeviceToHost, s));
     FCT_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < P; ++q) iters[(size_t)q] = fd[q] != 0 ? fd[q] - 1 : last_queued;
   } else {
@@ -1547,9 +1538,8 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
       if (st != FCT_OK) return st;
       total_queued += last_queued;
       budget -= last_queued;
-      FCT_HIP(hipMemcpyAsync(fd, a.done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(fr, a.ring, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, s));
-      FCT_HIP(hipMemcpyAsync(ws->h_flags, a.flags, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+      FCT_HIP(hipMemcpyAsync(ws->h_status + 2 * status_bytes(P), ws->d_status,
+                             status_bytes(P), hipMemcpyDeviceToHost, s));
       FCT_HIP(hipStreamSynchronize(s));
       bool any_cont = false;
       for (int q = 0; q < P; ++q) {

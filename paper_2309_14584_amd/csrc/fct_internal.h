@@ -397,6 +397,19 @@ struct fct_plan {
   int64_t device_bytes = 0;
 };
 
+// Layout of the solve status block of nprob problems (bytes).
+inline size_t status_bytes(int64_t P) { return (size_t)80 * (size_t)P; }
+struct StatusView {
+  double* ring;      // [P][8]
+  double* gamma0;    // [P]
+  int32_t* done;     // [P]
+  int32_t* flags;    // [P]
+};
+inline StatusView status_view(unsigned char* base, int64_t P) {
+  return {reinterpret_cast<double*>(base), reinterpret_cast<double*>(base + 64 * P),
+          reinterpret_cast<int32_t*>(base + 72 * P), reinterpret_cast<int32_t*>(base + 76 * P)};
+}
+
 struct fct_ws {
   int device = 0;
   const fct_plan* plan = nullptr;
@@ -421,20 +434,23 @@ struct fct_ws {
   int32_t* d_nb_ovf = nullptr;     // [max(1, overflow entries)]
   int32_t* d_nb_diag = nullptr;    // [n]
   double* d_bperm = nullptr;       // [M] rows in (grid, bin) order (rows_by_member plans)
-  double* d_ring = nullptr;        // [nprob][8]
-  double* d_gamma0 = nullptr;      // [nprob]
-  int32_t* d_done = nullptr;       // [nprob]
-  int32_t* d_flags = nullptr;      // [nprob]
+  // per-problem solve status, one allocation so that a chunk check copies it
+  // to the host at once: ring [nprob][8], gamma0 [nprob] (doubles), then
+  // done [nprob], flags [nprob] (int32); the four pointers are views of it
+  unsigned char* d_status = nullptr;
+  double* d_ring = nullptr;
+  double* d_gamma0 = nullptr;
+  int32_t* d_done = nullptr;
+  int32_t* d_flags = nullptr;
   int32_t* d_done_tmp = nullptr;   // [nprob] (timing launches)
   int32_t* d_state = nullptr;      // [4]
   int32_t* d_state_tmp = nullptr;  // [4]   (timing launches)
   int32_t* d_bar = nullptr;        // [4]   grid barrier (count, generation), abort flag
   int32_t fused[2] = {-1, -1};     // single-kernel workgroups per precision (-1: not yet known)
-  // pinned host copies: two in-flight chunk checks, then the final state
-  int32_t* h_done = nullptr;       // [3][nprob]
-  double* h_ring = nullptr;        // [3][nprob][8]
-  double* h_gamma0 = nullptr;      // [3][nprob]
-  int32_t* h_flags = nullptr;      // [nprob]
+  // pinned host copies of the status block: two in-flight chunk checks,
+  // then the final state (slot 2); h_flags is slot 2's flags
+  unsigned char* h_status = nullptr;   // [3][status_bytes(nprob)]
+  int32_t* h_flags = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // FP64, FP32 iteration chunks
   hipStream_t graph_stream = nullptr;
