@@ -190,11 +190,15 @@ typedef struct fct_solve_opts {
                            gradients on A^T A c = A^T b with one reduction per
                            iteration (Chronopoulos-Gear recurrences; the CGLS
                            iterates in exact arithmetic, rounded differently):
-                           one kernel per iteration that forms A^T A r by
-                           gathering each row's members, instead of the row
-                           and column kernels; for problems whose kernels are
-                           bound by latency.  Timing mode then reports that
-                           kernel in rows_kernel_us (cols_kernel_us 0).
+                           one kernel per iteration that forms A^T A r from
+                           each column's neighbour list (built on first use
+                           with this workspace), instead of the row and
+                           column kernels; about a quarter of their memory
+                           traffic, faster on small problems, not on the D=6
+                           workload, where both are bound by launch and gather
+                           latency.  Implied for FCT_PLAN_GAUSS plans.  Timing
+                           mode then reports that kernel in rows_kernel_us
+                           (cols_kernel_us 0).
                            FCT_EINVAL with a batch, FP32 modes or
                            single_kernel.  0 (default): CGLS */
 } fct_solve_opts;
