@@ -246,18 +246,21 @@ __global__ __launch_bounds__(kCg1Block) void cg1_init_kernel(CglsArgs a) {
   }
 }
 
+// Launched with an even iteration base (the host queues chunks of even
+// length, except a last one that ends at the iteration limit), so the
+// buffer parity is that of rel, a launch argument: no operand address waits
+// for a load of the base.
 __global__ __launch_bounds__(kCg1Block) void cg1_kernel(CglsArgs a, int rel) {
   const int done = a.done[0];
-  const int k = a.state[0] + rel;
-  const int q = k & 1;
+  const int q = rel & 1;
   const double4* cur = a.cg[q];
   double4* nxt = a.cg[q ^ 1];
   const int32_t nb = a.cg1_nblk;
   const double* pin = a.cg_part + (int64_t)q * 2 * nb;
   double* pout = a.cg_part + (int64_t)(q ^ 1) * 2 * nb;
-  if (done != 0) return;
 
-  // operands that do not depend on the scalars of iteration k
+  // operands that do not depend on the scalars of iteration k (issued
+  // before the stop flag is tested)
   const int32_t j = blockIdx.x * kCg1Block + threadIdx.x;
   const bool active = j < a.cg1_n;
   const int32_t jc = active ? j : 0;
@@ -274,6 +277,8 @@ __global__ __launch_bounds__(kCg1Block) void cg1_kernel(CglsArgs a, int rel) {
       R = fma(sg, v.x, R); W = fma(sg, v.y, W); S = fma(sg, v.z, S);
     });
   }
+  if (done != 0) return;
+  const int k = a.state[0] + rel;
 
   const double2 gd = wave_sum2(gp, dp);
   const double gamma = gd.x, delta = gd.y;

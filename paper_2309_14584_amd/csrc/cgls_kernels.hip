@@ -234,6 +234,45 @@ template <> struct BatchOf<double2> { static constexpr int value = 6; };
 // belongs to a workgroup that reaches the same stop decision from the same
 // scalars before it would use any skipped operand.  A single problem never
 // pays for the extra dependent load.
+// Block descriptors of the iteration kernels: formed from the arguments for
+// a single problem (regular blocks; every load that needs a row or column
+// index then waits for no table read), loaded from the tables otherwise.
+__device__ __forceinline__ RowBlock row_block(const CglsArgs& a) {
+  if (a.reg_M > 0) {
+    RowBlock r;
+    r.prob = 0;
+    r.row0 = (int32_t)blockIdx.x * kBlock;
+    r.row_end = min(a.reg_M, r.row0 + kBlock);
+    r.cblk_off = 0;
+    r.ncblk = (int32_t)a.ncblk;
+    r.first = blockIdx.x == 0 ? 1 : 0;
+    r.pslot = (int32_t)blockIdx.x;
+    r.pad1 = 0;
+    return r;
+  }
+  return a.rblk[blockIdx.x];
+}
+
+__device__ __forceinline__ ColBlock col_block(const CglsArgs& a) {
+  if (a.reg_n > 0) {
+    ColBlock c;
+    c.prob = 0;
+    c.col0 = (int32_t)blockIdx.x * kBlock;
+    c.col_end = min(a.reg_n, c.col0 + kBlock);
+    c.col_off = 0;
+    c.rblk_off = 0;
+    c.nrblk = (int32_t)a.nrblk;
+    c.K = a.reg_K;
+    c.n = a.reg_n;
+    c.rmap_off = 0;
+    c.first = blockIdx.x == 0 ? 1 : 0;
+    c.pad0 = 0;
+    c.pad1 = 0;
+    return c;
+  }
+  return a.cblk[blockIdx.x];
+}
+
 __device__ __forceinline__ bool live_problem(const CglsArgs& a, int p) {
   return a.nprob == 1 || __builtin_amdgcn_readfirstlane(a.done[p]) == 0;
 }
@@ -357,7 +396,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void cgls_rows_kernel(CglsArgs a, int rel) {
   __shared__ double sh[kShSlots];
   __shared__ int s_done;
-  const RowBlock bd = a.rblk[blockIdx.x];            // uniform: one scalar load
+  const RowBlock bd = row_block(a);                  // uniform
   const int p = bd.prob;
   // the problem's stop flag is read once per workgroup (thread 0, through
   // LDS), so all of its waves take the same branch even if the problem's
@@ -464,7 +503,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void cgls_cols_kernel(CglsArgs a, int rel) {
   __shared__ double sh[kShSlots];
   __shared__ int s_done;
-  const ColBlock bd = a.cblk[blockIdx.x];
+  const ColBlock bd = col_block(a);
   const int p = bd.prob;
   if (threadIdx.x == 0) s_done = a.done[p];
   const int base = a.state[0];

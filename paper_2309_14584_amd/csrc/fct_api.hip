@@ -1323,6 +1323,9 @@ static fct_status cgls_loop(const fct_plan* p, fct_ws* ws, const CglsArgs& a, in
         want = std::min(want, std::max(warm / 2, (remaining + 1) / 2));
       int c = std::min(want, remaining);
       if (c < 1) c = 1;
+      // the one-reduction kernel takes its buffer parity from rel: keep every
+      // chunk's base even (only a chunk that ends at maxit may be odd)
+      if (a.cg1 && (c & 1) && queued + c < maxit) ++c;
       ++nchunks;
       if (fused > 0) {
         FCT_HIP(launch_cgls_fused(a, c, fused, ws->d_bar, ws->d_bar + 2, s));
@@ -1465,6 +1468,11 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   a.state = ws->d_state;
   a.r64 = ws->d_r64; a.part_true = ws->d_part_true; a.gtrue0 = ws->d_gtrue;
   a.gtrue = ws->d_gtrue + P; a.outer_done = ws->d_outer;
+  if (P == 1) {
+    a.reg_M = (int32_t)p->M;
+    a.reg_n = (int32_t)p->n;
+    a.reg_K = p->K;
+  }
   if (o.one_reduction != 0) {
     st = ensure_neighbours(p, ws, s);
     if (st != FCT_OK) return st;

@@ -269,6 +269,11 @@ struct CglsArgs {
   const int32_t* nb_off;
   const int32_t* nb_ovf;
   const int32_t* nb_diag;   // [n] diagonal of A^T A
+  // a single problem's row and column blocks are regular (block b covers
+  // [b kBlock, min(end, (b + 1) kBlock))): its rows, columns and grids, so
+  // the iteration kernels form their descriptors instead of loading them
+  // (0: read the block tables)
+  int32_t reg_M, reg_n, reg_K;
   int32_t cg1_n;      // columns
   int32_t cg1_K;      // grids
   int32_t cg1_nblk;   // one-wave workgroups (kCg1Block columns each)
