@@ -321,6 +321,14 @@ __device__ __forceinline__ RowOps<P, NR> rows_load(const CglsArgs& a, const RowB
 // q = A p for the block's rows with p_k = s_k + beta p_{k-1} formed on the
 // fly, r updated, and the per-wave partials of ||q||^2 (no barrier: the
 // consumer adds the four waves of each block in order).
+// FP64 rows with more than kLongRow entries (a dimension that most grids do
+// not resolve collects many columns in one bin) are summed by the whole
+// wave: lane i adds entries i, i + 64, ... of the run in order, then a fixed
+// butterfly; shorter rows, and every row of the FP32 rounds, are summed by
+// their own lane in perm order.  Either way a row's sum does not depend on
+// the launch it is part of.
+constexpr int32_t kLongRow = 32;
+
 template <typename P, bool NR>
 __device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& bd,
                                             const RowOps<P, NR>& o, double beta,
@@ -328,16 +336,19 @@ __device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& b
   typedef typename RawOf<P>::type R;
   const R* const psr = static_cast<const R*>(a.ps);
   double qv = 0.0;
-  if (o.active) {
+  bool is_long = false;
+  if (!NR && o.active && o.e.w < -1)
+    is_long = a.seg_off[o.row + 1] - a.seg_off[o.row] > kLongRow;
+  // own rows first (the prefetched pairs are consumed before the wave loop)
+  if (o.active && !is_long) {
     const int4 e = o.e;
-    const double2 rq_old = raw_d2(o.rq_raw);
     const double2 v0 = raw_d2(o.r0), v1 = raw_d2(o.r1), v2 = raw_d2(o.r2), v3 = raw_d2(o.r3);
     // terms in perm order: p_k = s_k + beta p_{k-1} for each aliased column
     if (e.x >= 0) qv += direction<P>(beta, v0);
     if (e.y >= 0) qv += direction<P>(beta, v1);
     if (e.z >= 0) qv += direction<P>(beta, v2);
     if (e.w >= 0) qv += direction<P>(beta, v3);
-    if (e.w < -1) {                                  // long row: rest of its run in perm
+    if (e.w < -1) {                                  // row of 5..kLongRow: rest of its run
       const int32_t t1 = a.seg_off[o.row + 1];
       constexpr int kBatch = BatchOf<P>::value;
       for (int32_t t0 = -(e.w + 2); t0 < t1; t0 += kBatch) {
@@ -356,6 +367,31 @@ __device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& b
         }
       }
     }
+  }
+  // long rows of the wave, one after another, by all 64 lanes
+  if (!NR) {
+    uint64_t pending = __ballot(is_long);
+    while (pending != 0) {                           // wave-uniform
+      const int src = __ffsll((unsigned long long)pending) - 1;
+      pending &= pending - 1;
+      const int32_t row = __shfl(o.row, src, 64);
+      const int32_t t0 = a.seg_off[row], t1 = a.seg_off[row + 1];
+      const int lane = (int)(threadIdx.x & 63);
+      double part = 0.0;
+      for (int32_t t = t0 + lane; t < t1; t += 2 * 64) {
+        const int32_t j0 = a.perm[t];
+        const int32_t j1 = t + 64 < t1 ? a.perm[t + 64] : -1;
+        const R w0 = psr[j0];
+        const R w1 = j1 >= 0 ? psr[j1] : raw_zero<R>();
+        part += direction<P>(beta, raw_d2(w0));
+        if (j1 >= 0) part += direction<P>(beta, raw_d2(w1));
+      }
+      const double tot = wave_sum(part);
+      if (lane == src) qv = tot;
+    }
+  }
+  if (o.active) {
+    const double2 rq_old = raw_d2(o.rq_raw);
     if (NR) static_cast<float*>(a.rq)[o.row] = (float)qv;     // q alone, FP32
     else static_cast<P*>(a.rq)[o.row] = make_pair<P>(fma(-alpha_prev, rq_old.y, rq_old.x), qv);
   }
