@@ -327,7 +327,7 @@ __device__ __forceinline__ RowOps<P, NR> rows_load(const CglsArgs& a, const RowB
 // butterfly; shorter rows, and every row of the FP32 rounds, are summed by
 // their own lane in perm order.  Either way a row's sum does not depend on
 // the launch it is part of.
-constexpr int32_t kLongRow = 32;
+constexpr int32_t kLongRow = 96;
 
 template <typename P, bool NR>
 __device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& bd,
@@ -336,9 +336,14 @@ __device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& b
   typedef typename RawOf<P>::type R;
   const R* const psr = static_cast<const R*>(a.ps);
   double qv = 0.0;
-  bool is_long = false;
-  if (!NR && o.active && o.e.w < -1)
-    is_long = a.seg_off[o.row + 1] - a.seg_off[o.row] > kLongRow;
+  // a row of more than four entries: its run is [t_beg, t_end) in perm (the
+  // ELL marker holds the position of its fourth entry)
+  int32_t t_beg = 0, t_end = 0;
+  if (o.active && o.e.w < -1) {
+    t_beg = -(o.e.w + 2) - 3;
+    t_end = a.seg_off[o.row + 1];
+  }
+  const bool is_long = !NR && t_end - t_beg > kLongRow;
   // own rows first (the prefetched pairs are consumed before the wave loop)
   if (o.active && !is_long) {
     const int4 e = o.e;
@@ -349,7 +354,7 @@ __device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& b
     if (e.z >= 0) qv += direction<P>(beta, v2);
     if (e.w >= 0) qv += direction<P>(beta, v3);
     if (e.w < -1) {                                  // row of 5..kLongRow: rest of its run
-      const int32_t t1 = a.seg_off[o.row + 1];
+      const int32_t t1 = t_end;
       constexpr int kBatch = BatchOf<P>::value;
       for (int32_t t0 = -(e.w + 2); t0 < t1; t0 += kBatch) {
         // kBatch independent index loads, then kBatch independent gathers,
@@ -374,8 +379,7 @@ __device__ __forceinline__ void rows_finish(const CglsArgs& a, const RowBlock& b
     while (pending != 0) {                           // wave-uniform
       const int src = __ffsll((unsigned long long)pending) - 1;
       pending &= pending - 1;
-      const int32_t row = __shfl(o.row, src, 64);
-      const int32_t t0 = a.seg_off[row], t1 = a.seg_off[row + 1];
+      const int32_t t0 = __shfl(t_beg, src, 64), t1 = __shfl(t_end, src, 64);
       const int lane = (int)(threadIdx.x & 63);
       double part = 0.0;
       for (int32_t t = t0 + lane; t < t1; t += 2 * 64) {
