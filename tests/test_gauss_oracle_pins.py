@@ -115,3 +115,22 @@ def test_rank_precheck_detects_dependent_columns():
     # T_{N+1} vanishes on every grid -> zero column
     assert not G.rank_precheck_gauss(np.array([[0], [3]]), [[2], [2]])
     assert G.rank_precheck_gauss(S, [[3]])
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 6, 11])
+def test_signed_fold_rule_matches_lemma(N):
+    """The closed fold-and-sign rule (r = a mod 2(N+1), m = min(r, 2(N+1) - r),
+    sign (-1)^(a div 2(N+1)) for r < N+1, its negation for r > N+1, zero at
+    r = N+1) against the Delta-based aliasing matrix of Lemma 3.1."""
+    g = N + 1
+    S = np.arange(0, 9 * g + 3)[:, None]
+    bins, w = G.signed_alias(S, [N])
+    for a in range(S.shape[0]):
+        r = a % (2 * g)
+        odd = (a // (2 * g)) % 2
+        if r == g:
+            assert w[a] == 0
+            continue
+        m = r if r < g else 2 * g - r
+        s = (-1 if odd else 1) if r < g else (1 if odd else -1)
+        assert bins[a] == m and w[a] == s

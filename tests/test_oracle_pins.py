@@ -633,3 +633,15 @@ def test_f3_sparse_support_recovers_exactly():
     assert p.D == 100 and len(np.unique(p.support, axis=0)) == p.n
     c, plan, _ = O.fct_solve(p.support, p.grids, O.sample_problem(p), "auto")
     assert O.max_rel_err(c, p.coeffs) < 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_d20_cover_resolves_every_d_set(d):
+    """The D=20 grid covers used by the serving and long-row workloads
+    resolve every set of d dimensions in some grid (degree d there)."""
+    from itertools import combinations
+    G = W.d20_grids(4, d, 8)
+    resolved = [frozenset(np.nonzero(g)[0].tolist()) for g in G]
+    assert all(int(v) in (0, d) for v in np.unique(G))
+    for c in combinations(range(20), d):
+        assert any(set(c) <= r for r in resolved)
