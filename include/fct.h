@@ -138,8 +138,8 @@ typedef enum fct_solve_mode {
  * read p and r nearly in order instead of at random.  perm, seg_off, bin_id
  * and rowmap (fct_plan_export) follow this order; b from fct_dct is in it
  * (the transform writes the bins in bin order to the workspace, then gathers
- * them), so fct_dct needs the workspace.  Single problem (not batched), not
- * with FCT_PLAN_GAUSS. */
+ * them), so fct_dct needs the workspace.  Such plans may be batched (each
+ * problem keeps its own order); not with FCT_PLAN_GAUSS. */
 #define FCT_PLAN_ROWS_BY_MEMBER 4u
 
 typedef struct fct_plan fct_plan;

@@ -672,10 +672,6 @@ fct_status fct_batch_create(int32_t count, const fct_plan* const* plans, hipStre
     const fct_plan* s = plans[q];
     if (!s || s->nprob != 1) { set_error("plan %d is NULL or already a batch", q); return FCT_EINVAL; }
     if (s->gauss) { set_error("plan %d is a Gauss-grid plan (not batched)", q); return FCT_EINVAL; }
-    if (s->rows_by_member) {
-      set_error("plan %d orders rows by first member (not batched)", q);
-      return FCT_EINVAL;
-    }
     if (s->device != dev) { set_error("plan %d lives on another device", q); return FCT_EINVAL; }
     Lsum += (int64_t)s->K * s->n;
     Msum += s->M;
@@ -700,6 +696,15 @@ fct_status fct_batch_create(int32_t count, const fct_plan* const* plans, hipStre
   FCT_HIP(dalloc(&p->d_bin_id, Msum, bytes));
   FCT_HIP(dalloc(&p->d_rowmap, Lsum, bytes));
   FCT_HIP(dalloc(&p->d_ell, Msum, bytes));
+  // a batch with a plan whose rows are ordered by first member keeps the
+  // (grid, bin) order of every problem for its transforms, with the maps
+  // between the two (identity for the other problems)
+  for (int32_t q = 0; q < count; ++q) p->rows_by_member |= plans[q]->rows_by_member;
+  if (p->rows_by_member) {
+    FCT_HIP(dalloc(&p->d_bin_dct, Msum, bytes));
+    FCT_HIP(dalloc(&p->d_row_old, Msum, bytes));
+    FCT_HIP(dalloc(&p->d_row_new, Msum, bytes));
+  }
 
   p->grid_goff.push_back(0);
   p->point_off.push_back(0);
@@ -722,6 +727,17 @@ fct_status fct_batch_create(int32_t count, const fct_plan* const* plans, hipStre
     FCT_HIP(launch_copy_ell(p->d_ell + moff, s->d_ell, s->M, (int32_t)noff, (int32_t)loff, stream));
     FCT_HIP(hipMemcpyAsync(p->d_bin_id + moff, s->d_bin_id, sizeof(int64_t) * s->M,
                            hipMemcpyDeviceToDevice, stream));
+    if (p->rows_by_member) {
+      FCT_HIP(hipMemcpyAsync(p->d_bin_dct + moff, s->d_bin_dct ? s->d_bin_dct : s->d_bin_id,
+                             sizeof(int64_t) * s->M, hipMemcpyDeviceToDevice, stream));
+      if (s->rows_by_member) {
+        FCT_HIP(launch_copy_add_i32(p->d_row_old + moff, s->d_row_old, s->M, (int32_t)moff, stream));
+        FCT_HIP(launch_copy_add_i32(p->d_row_new + moff, s->d_row_new, s->M, (int32_t)moff, stream));
+      } else {
+        FCT_HIP(launch_iota_i32(p->d_row_old + moff, s->M, (int32_t)moff, stream));
+        FCT_HIP(launch_iota_i32(p->d_row_new + moff, s->M, (int32_t)moff, stream));
+      }
+    }
     for (int32_t l = 0; l < s->K; ++l) {
       const int32_t D = s->grid_D[(size_t)l];
       const int32_t* g = &s->grids[(size_t)s->grid_goff[(size_t)l]];

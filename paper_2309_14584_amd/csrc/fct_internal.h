@@ -96,6 +96,8 @@ hipError_t launch_rows_gather(const double* src, const int32_t* idx, int64_t M, 
                               hipStream_t s);
 hipError_t launch_rows_scatter(const double* src, const int32_t* idx, int64_t M, double* dst,
                                hipStream_t s);
+// dst[i] = start + i
+hipError_t launch_iota_i32(int32_t* dst, int64_t count, int32_t start, hipStream_t s);
 // inv[idx[r]] = r for a permutation idx of 0..M-1
 hipError_t launch_index_inverse(const int32_t* idx, int64_t M, int32_t* inv, hipStream_t s);
 // gauss: Chebyshev-Gauss nodes and the DCT-II instead of Lobatto and DCT-I
@@ -352,7 +354,7 @@ struct fct_plan {
   int32_t maxdeg = 0;
   int32_t smax = 0;                // largest support entry (single problem)
   int32_t gauss = 0;               // Gauss grids / DCT-II operator (single problem)
-  int32_t rows_by_member = 0;      // each grid's rows ordered by first member (single problem)
+  int32_t rows_by_member = 0;      // rows ordered by first member (in a batch: some problem's)
   std::vector<int32_t> grid_D;     // [K] dimension of each grid's problem
   std::vector<int64_t> grid_goff;  // [K+1] offsets of each grid's degrees in `grids`
   std::vector<int32_t> grids;      // degrees, grid after grid

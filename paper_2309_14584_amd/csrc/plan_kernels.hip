@@ -337,6 +337,12 @@ __global__ __launch_bounds__(kBlock) void rows_gather_kernel(const double* __res
   if (r < M) dst[r] = src[idx[r]];
 }
 
+__global__ __launch_bounds__(kBlock) void iota_i32_kernel(int32_t* __restrict__ dst, int64_t count,
+                                                          int32_t start) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = start + (int32_t)i;
+}
+
 __global__ __launch_bounds__(kBlock) void index_inverse_kernel(const int32_t* __restrict__ idx,
                                                                int64_t M,
                                                                int32_t* __restrict__ inv) {
@@ -512,6 +518,13 @@ hipError_t launch_rows_gather(const double* src, const int32_t* idx, int64_t M, 
   if (M <= 0) return hipSuccess;
   hipLaunchKernelGGL(rows_gather_kernel, dim3((unsigned)ceil_div(M, kBlock)), dim3(kBlock), 0, s,
                      src, idx, M, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota_i32(int32_t* dst, int64_t count, int32_t start, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_i32_kernel, dim3((unsigned)ceil_div(count, kBlock)), dim3(kBlock), 0, s,
+                     dst, count, start);
   return hipGetLastError();
 }
 

@@ -125,15 +125,37 @@ def test_rows_by_member_sparse_d100(fct):
     plan.close()
 
 
+def test_rows_by_member_in_a_batch(fct):
+    """A batch of reordered and plain plans: every problem's b and
+    coefficients are the bits it gives alone (FP64 and mixed solves)."""
+    probs = [CASES[1], CASES[0], W.small_problem(4, 5, 5, 2, 9, 7, W.FAMILY_GAUSS)]
+    flags = [True, False, True]
+    plans = [fct.Plan(p.support, p.grids, rows_by_member=f) for p, f in zip(probs, flags)]
+    batch = fct.Plan.batch(plans)
+    rng = np.random.default_rng(43)
+    x = rng.standard_normal(batch.P)
+    bb = _host(batch.dct(_dev(x)))
+    alone_b, poff, roff = [], 0, 0
+    for pl in plans:
+        alone_b.append(_host(pl.dct(_dev(x[poff:poff + pl.P]))))
+        assert np.array_equal(bb[roff:roff + pl.M], alone_b[-1])
+        poff += pl.P
+        roff += pl.M
+    for mode in (fct.SOLVE_F64, fct.SOLVE_F32_REFINE):
+        cb, _ = batch.solve(_dev(bb), mode=mode, raise_on_noconv=False)
+        cb = _host(cb)
+        coff = 0
+        for pl, b in zip(plans, alone_b):
+            ca, _ = pl.solve(_dev(b), mode=mode, raise_on_noconv=False)
+            assert np.array_equal(cb[coff:coff + pl.n], _host(ca)), mode
+            coff += pl.n
+    batch.close()
+    for pl in plans:
+        pl.close()
+
+
 def test_rows_by_member_rejections(fct):
     prob = CASES[0]
-    plan = fct.Plan(prob.support, prob.grids, rows_by_member=True)
-    other = fct.Plan(prob.support, prob.grids)
-    with pytest.raises(fct.FctError) as ei:
-        fct.Plan.batch([other, plan])
-    assert ei.value.status == fct.FCT_EINVAL
     with pytest.raises(fct.FctError) as ei:
         fct.Plan(prob.support, prob.grids, rows_by_member=True, gauss=True)
     assert ei.value.status == fct.FCT_EINVAL
-    other.close()
-    plan.close()
