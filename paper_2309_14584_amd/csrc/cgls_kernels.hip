@@ -494,7 +494,7 @@ __device__ __forceinline__ ColOps<P, NR> cols_load(const CglsArgs& a, const ColB
 
 // p_k stored, c_{k+1} = c_k + alpha p_k, s_{k+1}, and the block's partial of
 // ||s_{k+1}||^2 into part_s[slot].
-template <typename P, bool NR>
+template <typename P, bool NR, int BATCH = BatchOf<P>::value>
 __device__ __forceinline__ void cols_finish(const CglsArgs& a, const ColBlock& bd,
                                             const ColOps<P, NR>& o, double alpha, double beta,
                                             double* sh, int64_t slot) {
@@ -516,7 +516,7 @@ __device__ __forceinline__ void cols_finish(const CglsArgs& a, const ColBlock& b
       }
     }
     // further grids kBatch at a time: independent loads, sums in grid order
-    constexpr int kBatch = BatchOf<P>::value;
+    constexpr int kBatch = BATCH;
     for (int l0 = kPrefetch; l0 < bd.K; l0 += kBatch) {
       G vv[kBatch];
 #pragma unroll
@@ -538,8 +538,8 @@ __device__ __forceinline__ void cols_finish(const CglsArgs& a, const ColBlock& b
   if (threadIdx.x == 0) a.part_s[slot] = part;
 }
 
-template <typename P, bool NR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+template <typename P, bool NR, int BATCH = BatchOf<P>::value, int WAVES = 8>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 void cgls_cols_kernel(CglsArgs a, int rel) {
   __shared__ double sh[kShSlots];
   __shared__ int s_done;
@@ -562,7 +562,7 @@ void cgls_cols_kernel(CglsArgs a, int rel) {
   }
   const double alpha = gamma / delta;
   if (bd.first && threadIdx.x == 0) a.ring[p * 8 + 4 + (k & 3)] = alpha;
-  cols_finish<P, NR>(a, bd, o, alpha, beta, sh, blockIdx.x);
+  cols_finish<P, NR, BATCH>(a, bd, o, alpha, beta, sh, blockIdx.x);
 }
 
 // ---- one problem: the whole iteration in one kernel ----
@@ -992,6 +992,10 @@ int32_t lds_unit_capacity(int device) {
 hipError_t launch_cgls_cols(const CglsArgs& a, int rel, hipStream_t s) {
   if (a.fp32)
     hipLaunchKernelGGL((cgls_cols_kernel<float2, true>), dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, rel);
+  else if (a.max_K > kDeepColsK)
+    // many grids per column: deeper batches of independent loads (the sums
+    // keep grid order, so the bits are those of the default kernel)
+    hipLaunchKernelGGL((cgls_cols_kernel<double2, false, 16, 4>), dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, rel);
   else
     hipLaunchKernelGGL((cgls_cols_kernel<double2, false>), dim3((unsigned)a.ncblk), dim3(kBlock), 0, s, a, rel);
   return hipGetLastError();

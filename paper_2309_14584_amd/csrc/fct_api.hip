@@ -1484,6 +1484,7 @@ fct_status fct_solve(const fct_plan* p, const double* d_b, double* d_c,
   a.state = ws->d_state;
   a.r64 = ws->d_r64; a.part_true = ws->d_part_true; a.gtrue0 = ws->d_gtrue;
   a.gtrue = ws->d_gtrue + P; a.outer_done = ws->d_outer;
+  for (const auto& pi : p->probs) a.max_K = std::max(a.max_K, pi.K);
   if (P == 1) {
     a.reg_M = (int32_t)p->M;
     a.reg_n = (int32_t)p->n;

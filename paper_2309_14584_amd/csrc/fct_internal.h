@@ -276,11 +276,13 @@ struct CglsArgs {
   // the iteration kernels form their descriptors instead of loading them
   // (0: read the block tables)
   int32_t reg_M, reg_n, reg_K;
+  int32_t max_K;      // most grids of a problem (column-kernel batch depth)
   int32_t cg1_n;      // columns
   int32_t cg1_K;      // grids
   int32_t cg1_nblk;   // one-wave workgroups (kCg1Block columns each)
 };
 constexpr int kCg1Block = 64;
+constexpr int kDeepColsK = 64;    // above: the FP64 column kernel loads 16 grids at a time
 constexpr int kNbSlots = 8;
 hipError_t launch_cgls_init(const CglsArgs& a, const double* b, bool warm, hipStream_t s);
 // one-reduction CG: init after launch_cgls_init, one kernel per iteration
